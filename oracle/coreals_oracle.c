@@ -1,0 +1,386 @@
+/*
+ * FP64 CPU oracle for core-elements subsampled ALS.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It shares
+ * no code, header, table or helper with the HIP library.
+ *
+ * What it computes (Xue, Li, Zhang, Meng, "Core-elements Subsampling for
+ * Alternating Least Squares"):
+ *
+ *  - objective f(U, M) with the weighted lambda penalty   (Section 2.1, eq. for f)
+ *  - the full-data row update                              (Section 2.1, eq. (U)/(M))
+ *  - core-elements subsampling CES: per column of the design matrix X keep the
+ *    s = floor(|I_i| r) entries of largest magnitude        (Section 3, Algorithm 1
+ *                                                             and the selection rule)
+ *  - the core estimator u = (X*^T X + lambda n_i E)^-1 X*^T y
+ *                                                          (Section 3, eq. core_ui/core_mj)
+ *  - one half-sweep of Core-ALS over all rows              (Section 3, Algorithm 2)
+ *
+ * Readings where the paper leaves a choice open:
+ *  - ties in the top-s are broken by smaller position first;
+ *  - s = min(n, max(min_keep, floor(n num / den))) in 64-bit integers;
+ *  - an empty row gets the zero vector (counted);
+ *  - a core system whose partial-pivoting LU meets a pivot with
+ *    |pivot| <= n_f 2^-52 max|A| is replaced by the full-data row update
+ *    (eq. (U)), solved by Cholesky (counted as a singular fallback).
+ *
+ * All arithmetic is double precision.  Input factor matrices are double
+ * (callers widen fp32 arrays exactly).  OpenMP parallelises over rows only;
+ * each row's arithmetic is sequential and in the order written here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_OK 0
+#define ORA_E_ARG 1
+#define ORA_E_INDEX 2
+#define ORA_E_VALUE 3
+
+int ora_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Problem statement (Section 2.1): every observed index lies inside the
+ * matrix, a row lists each column once (ascending here), values are finite. */
+int ora_validate(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr,
+                 const int32_t *col_idx, const float *val) {
+    if (n_rows < 0 || n_cols < 0) return ORA_E_ARG;
+    if (row_ptr[0] != 0) return ORA_E_INDEX;
+    for (int64_t i = 0; i < n_rows; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return ORA_E_INDEX;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col_idx[e] < 0 || col_idx[e] >= n_cols) return ORA_E_INDEX;
+            if (e > row_ptr[i] && col_idx[e] <= col_idx[e - 1]) return ORA_E_INDEX;
+            if (!isfinite((double)val[e])) return ORA_E_VALUE;
+        }
+    }
+    return ORA_OK;
+}
+
+/* Column view of R: the item half-sweep regresses over I_j^M (Section 2.1). */
+void ora_transpose(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr,
+                   const int32_t *col_idx, const float *val,
+                   int64_t *col_ptr, int32_t *row_idx, float *val_t) {
+    int64_t *fill = (int64_t *)calloc((size_t)n_cols + 1, sizeof(int64_t));
+    for (int64_t j = 0; j <= n_cols; ++j) col_ptr[j] = 0;
+    for (int64_t e = 0; e < row_ptr[n_rows]; ++e) col_ptr[col_idx[e] + 1] += 1;
+    for (int64_t j = 0; j < n_cols; ++j) col_ptr[j + 1] += col_ptr[j];
+    for (int64_t i = 0; i < n_rows; ++i) {
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t j = col_idx[e];
+            int64_t dst = col_ptr[j] + fill[j]++;
+            row_idx[dst] = (int32_t)i;
+            val_t[dst] = val[e];
+        }
+    }
+    free(fill);
+}
+
+/* Budget s = floor(|I_i| r) (Section 3, selection rule), r = num/den,
+ * raised to min_keep and capped at n. */
+int64_t ora_budget(int64_t n, int64_t num, int64_t den, int64_t min_keep) {
+    int64_t s = (n * num) / den;
+    if (s < min_keep) s = min_keep;
+    if (s > n) s = n;
+    if (s < 0) s = 0;
+    return s;
+}
+
+typedef struct {
+    double mag;
+    int32_t pos;
+} ora_key;
+
+/* larger magnitude first; equal magnitudes: smaller position first */
+static int ora_key_cmp(const void *pa, const void *pb) {
+    const ora_key *a = (const ora_key *)pa, *b = (const ora_key *)pb;
+    if (a->mag > b->mag) return -1;
+    if (a->mag < b->mag) return 1;
+    return (a->pos > b->pos) - (a->pos < b->pos);
+}
+
+static int ora_int_cmp(const void *pa, const void *pb) {
+    int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+    return (a > b) - (a < b);
+}
+
+/* CES (Algorithm 1) on an n x nf matrix X (row-major): for every column a,
+ * the s positions whose |X[k][a]| are largest.  Writes pos[a*s + t], the
+ * positions of column a in ascending order. */
+void ora_select(int64_t n, int32_t nf, const double *X, int64_t s, int32_t *pos) {
+    if (s <= 0) return;
+    ora_key *keys = (ora_key *)malloc(sizeof(ora_key) * (size_t)(n > 0 ? n : 1));
+    for (int32_t a = 0; a < nf; ++a) {
+        for (int64_t k = 0; k < n; ++k) {
+            keys[k].mag = fabs(X[k * nf + a]);
+            keys[k].pos = (int32_t)k;
+        }
+        qsort(keys, (size_t)n, sizeof(ora_key), ora_key_cmp);
+        for (int64_t t = 0; t < s; ++t) pos[a * s + t] = keys[t].pos;
+        qsort(pos + a * s, (size_t)s, sizeof(int32_t), ora_int_cmp);
+    }
+    free(keys);
+}
+
+/* Solve A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+ * partial pivoting; the first row of largest |pivot| wins.  Returns 0 on
+ * success, 1 if some |pivot| <= tol. */
+static int ora_gepp(int32_t n, double *A, double *b, double tol) {
+    for (int32_t j = 0; j < n; ++j) {
+        int32_t p = j;
+        double best = fabs(A[j * n + j]);
+        for (int32_t i = j + 1; i < n; ++i) {
+            double v = fabs(A[i * n + j]);
+            if (v > best) { best = v; p = i; }
+        }
+        if (!(best > tol)) return 1;
+        if (p != j) {
+            for (int32_t c = 0; c < n; ++c) {
+                double t = A[j * n + c]; A[j * n + c] = A[p * n + c]; A[p * n + c] = t;
+            }
+            double t = b[j]; b[j] = b[p]; b[p] = t;
+        }
+        for (int32_t i = j + 1; i < n; ++i) {
+            double l = A[i * n + j] / A[j * n + j];
+            if (l == 0.0) continue;
+            for (int32_t c = j; c < n; ++c) A[i * n + c] -= l * A[j * n + c];
+            b[i] -= l * b[j];
+        }
+    }
+    for (int32_t j = n - 1; j >= 0; --j) {
+        double acc = b[j];
+        for (int32_t c = j + 1; c < n; ++c) acc -= A[j * n + c] * b[c];
+        b[j] = acc / A[j * n + j];
+    }
+    return 0;
+}
+
+/* Solve G x = b for symmetric positive definite G by Cholesky G = L L^T.
+ * Returns 1 if a diagonal is not positive. */
+static int ora_cholesky_solve(int32_t n, double *G, double *b) {
+    for (int32_t j = 0; j < n; ++j) {
+        double d = G[j * n + j];
+        for (int32_t c = 0; c < j; ++c) d -= G[j * n + c] * G[j * n + c];
+        if (!(d > 0.0)) return 1;
+        d = sqrt(d);
+        G[j * n + j] = d;
+        for (int32_t i = j + 1; i < n; ++i) {
+            double v = G[i * n + j];
+            for (int32_t c = 0; c < j; ++c) v -= G[i * n + c] * G[j * n + c];
+            G[i * n + j] = v / d;
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        double v = b[j];
+        for (int32_t c = 0; c < j; ++c) v -= G[j * n + c] * b[c];
+        b[j] = v / G[j * n + j];
+    }
+    for (int32_t j = n - 1; j >= 0; --j) {
+        double v = b[j];
+        for (int32_t c = j + 1; c < n; ++c) v -= G[c * n + j] * b[c];
+        b[j] = v / G[j * n + j];
+    }
+    return 0;
+}
+
+/* Full-data row update, eq. (U): (X^T X + lambda n E) u = X^T y. */
+static int ora_full_row(int64_t n, int32_t nf, const double *X, const double *y,
+                        double lam, double *u) {
+    double *G = (double *)calloc((size_t)nf * nf, sizeof(double));
+    for (int32_t a = 0; a < nf; ++a) {
+        for (int32_t c = 0; c < nf; ++c) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < n; ++k) acc += X[k * nf + a] * X[k * nf + c];
+            G[a * nf + c] = acc;
+        }
+        G[a * nf + a] += lam * (double)n;
+        double acc = 0.0;
+        for (int64_t k = 0; k < n; ++k) acc += X[k * nf + a] * y[k];
+        u[a] = acc;
+    }
+    int bad = ora_cholesky_solve(nf, G, u);
+    if (bad) for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+    free(G);
+    return bad;
+}
+
+/* One core regression, eq. core_ui: X is n x nf, y has n entries.
+ * Returns 0 normal, 1 empty row, 2 singular fallback taken. */
+int ora_core_row(int64_t n, int32_t nf, const double *X, const double *y, double lam,
+                 int64_t s, double *u) {
+    if (n == 0) {
+        for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+        return 1;
+    }
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)nf * (size_t)(s > 0 ? s : 1));
+    ora_select(n, nf, X, s, pos);
+    double *A = (double *)calloc((size_t)nf * nf, sizeof(double));
+    double *b = (double *)calloc((size_t)nf, sizeof(double));
+    /* row a of X*^T X: sum over the kept positions of column a */
+    for (int32_t a = 0; a < nf; ++a) {
+        for (int64_t t = 0; t < s; ++t) {
+            int64_t k = pos[a * s + t];
+            double xa = X[k * nf + a];
+            for (int32_t c = 0; c < nf; ++c) A[a * nf + c] += xa * X[k * nf + c];
+            b[a] += xa * y[k];
+        }
+        A[a * nf + a] += lam * (double)n;
+    }
+    double amax = 0.0;
+    for (int64_t e = 0; e < (int64_t)nf * nf; ++e) amax = fmax(amax, fabs(A[e]));
+    double tol = (double)nf * ldexp(1.0, -52) * amax;
+    int status = 0;
+    if (ora_gepp(nf, A, b, tol)) {
+        ora_full_row(n, nf, X, y, lam, u);
+        status = 2;
+    } else {
+        for (int32_t a = 0; a < nf; ++a) u[a] = b[a];
+    }
+    free(A);
+    free(b);
+    free(pos);
+    return status;
+}
+
+/* Gather the design matrix of one row: X[k] = other[col_idx[e_k]] (Section 2.1,
+ * the sub-matrix of the other factor whose rows are the observed columns). */
+static void ora_gather(int64_t beg, int64_t n, int32_t nf, const int32_t *col_idx,
+                       const float *val, const double *other, double *X, double *y) {
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t j = col_idx[beg + k];
+        for (int32_t a = 0; a < nf; ++a) X[k * nf + a] = other[j * nf + a];
+        y[k] = (double)val[beg + k];
+    }
+}
+
+/* One half-sweep of Algorithm 2: every row of a CSR regresses on `other`.
+ * out is n_rows x nf.  stats[0] counts empty rows, stats[1] singular fallbacks. */
+void ora_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr,
+                    const int32_t *col_idx, const float *val, const double *other,
+                    double lam, int64_t num, int64_t den, int64_t min_keep,
+                    double *out, int64_t *stats) {
+    int64_t n_empty = 0, n_fallback = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_empty, n_fallback)
+    for (int64_t i = 0; i < n_rows; ++i) {
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        ora_gather(beg, n, nf, col_idx, val, other, X, y);
+        int64_t s = ora_budget(n, num, den, min_keep);
+        int st = ora_core_row(n, nf, X, y, lam, s, out + i * nf);
+        if (st == 1) n_empty++;
+        if (st == 2) n_fallback++;
+        free(X);
+        free(y);
+    }
+    if (stats) {
+        stats[0] = n_empty;
+        stats[1] = n_fallback;
+    }
+}
+
+/* Same as ora_half_sweep restricted to the listed rows (for sampled checks
+ * at full size); out holds len(rows) x nf. */
+void ora_half_sweep_rows(int64_t n_list, const int64_t *rows, int32_t nf,
+                         const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                         const double *other, double lam, int64_t num, int64_t den,
+                         int64_t min_keep, double *out, int64_t *stats) {
+    int64_t n_empty = 0, n_fallback = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_empty, n_fallback)
+    for (int64_t t = 0; t < n_list; ++t) {
+        int64_t i = rows[t];
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        ora_gather(beg, n, nf, col_idx, val, other, X, y);
+        int64_t s = ora_budget(n, num, den, min_keep);
+        int st = ora_core_row(n, nf, X, y, lam, s, out + t * nf);
+        if (st == 1) n_empty++;
+        if (st == 2) n_fallback++;
+        free(X);
+        free(y);
+    }
+    if (stats) {
+        stats[0] = n_empty;
+        stats[1] = n_fallback;
+    }
+}
+
+/* CES positions for the listed rows: for row rows[t] with budget s, column a,
+ * writes s ascending positions at sel[sel_ptr[t] + a*s ...]. */
+void ora_core_select_rows(int64_t n_list, const int64_t *rows, int32_t nf,
+                          const int64_t *row_ptr, const int32_t *col_idx,
+                          const double *other, int64_t num, int64_t den, int64_t min_keep,
+                          const int64_t *sel_ptr, int32_t *sel) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_list; ++t) {
+        int64_t i = rows[t];
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t j = col_idx[beg + k];
+            for (int32_t a = 0; a < nf; ++a) X[k * nf + a] = other[j * nf + a];
+        }
+        int64_t s = ora_budget(n, num, den, min_keep);
+        ora_select(n, nf, X, s, sel + sel_ptr[t]);
+        free(X);
+    }
+}
+
+/* Objective (Section 2.1): out[0] = f = SSE + lambda (sum_i n_i |u_i|^2 +
+ * sum_j n_j |m_j|^2), out[1] = SSE, out[2] = RMSE = sqrt(SSE / nnz),
+ * out[3] = ReMSE = sqrt(SSE) / sqrt(sum r^2)  (Section 5.1). */
+void ora_objective(int64_t n_u, int64_t n_m, int32_t nf, const int64_t *row_ptr,
+                   const int32_t *col_idx, const float *val, const double *U,
+                   const double *M, double lam, double *out) {
+    double sse = 0.0, rr = 0.0, pen_u = 0.0, pen_m = 0.0;
+    int64_t nnz = row_ptr[n_u];
+    int64_t *deg_m = (int64_t *)calloc((size_t)n_m + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < nnz; ++e) deg_m[col_idx[e]] += 1;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : sse, rr, pen_u)
+    for (int64_t i = 0; i < n_u; ++i) {
+        double nrm = 0.0;
+        for (int32_t a = 0; a < nf; ++a) nrm += U[i * nf + a] * U[i * nf + a];
+        pen_u += (double)(row_ptr[i + 1] - row_ptr[i]) * nrm;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t j = col_idx[e];
+            double pred = 0.0;
+            for (int32_t a = 0; a < nf; ++a) pred += U[i * nf + a] * M[j * nf + a];
+            double r = (double)val[e] - pred;
+            sse += r * r;
+            rr += (double)val[e] * (double)val[e];
+        }
+    }
+    for (int64_t j = 0; j < n_m; ++j) {
+        double nrm = 0.0;
+        for (int32_t a = 0; a < nf; ++a) nrm += M[j * nf + a] * M[j * nf + a];
+        pen_m += (double)deg_m[j] * nrm;
+    }
+    free(deg_m);
+    out[0] = sse + lam * (pen_u + pen_m);
+    out[1] = sse;
+    out[2] = nnz > 0 ? sqrt(sse / (double)nnz) : 0.0;
+    out[3] = rr > 0.0 ? sqrt(sse) / sqrt(rr) : 0.0;
+}
