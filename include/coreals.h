@@ -1,0 +1,149 @@
+/*
+ * coreals.h -- C ABI of the MI355X (gfx950) library for core-elements
+ * subsampled alternating least squares.
+ *
+ * Method: Xue, Li, Zhang and Meng, "Core-elements Subsampling for Alternating
+ * Least Squares".  Problem statement in Section 2.1: a rating matrix R with
+ * observed index set I, rank n_f, factor matrices U (n_u x n_f) and
+ * M (n_m x n_f), and the weighted-lambda objective
+ *     f(U, M) = sum_I (r_ij - u_i m_j^T)^2 + lambda (sum_i n_i |u_i|^2 + sum_j n_j |m_j|^2).
+ * Core-ALS (Algorithm 2) alternates two half-sweeps.  Every row regression
+ * builds a sparse sketch X* of its design matrix X with CES (Algorithm 1:
+ * per column keep the floor(n_i r) entries of largest magnitude) and solves
+ *     (X*^T X + lambda n_i E) u = X*^T y            (eq. core_ui / core_mj).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the comment says (host).
+ *  - The caller owns every array, including the workspace; the library owns
+ *    only the opaque context (host memory).
+ *  - Every call is enqueued on the stream given in als_problem.stream
+ *    (a hipStream_t; NULL means the default stream).  Calls marked "syncs"
+ *    wait for that stream before returning.
+ *  - Calls return als_status and never abort.  als_last_error() describes the
+ *    most recent failure on a context.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - Index layout: CSR row_ptr int64[n_rows+1] starting at 0; col_idx int32,
+ *    strictly increasing inside a row; val float32.  Factor matrices are
+ *    float32, row-major, row stride n_f, and must not alias each other.
+ */
+#ifndef CORE_ALS_H
+#define CORE_ALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct als_ctx als_ctx;
+
+typedef enum {
+    ALS_OK = 0,
+    ALS_E_ARG = 1,     /* bad size, rate, precision or NULL pointer          */
+    ALS_E_INDEX = 2,   /* row_ptr not monotone, column out of range, repeated
+                          or unsorted column inside a row                      */
+    ALS_E_VALUE = 3,   /* NaN or Inf among the ratings (ALS_VALIDATE only)    */
+    ALS_E_NOMEM = 4,   /* workspace or output buffer too small                */
+    ALS_E_DEVICE = 5,  /* a HIP runtime error                                 */
+    ALS_E_STATE = 6    /* call not valid on this context                      */
+} als_status;
+
+typedef enum {
+    ALS_PREC_FP32 = 0,            /* FP32 Gram, FP32 solve                    */
+    ALS_PREC_BF16_IR = 1,         /* BF16 MFMA Gram (FP32 accumulate), FP32 LU,
+                                     one refinement step with an FP32 residual */
+    ALS_PREC_BF16_IR_FP64RES = 2  /* as above, refinement residual in FP64    */
+} als_precision;
+
+#define ALS_VALIDATE 1u /* check ratings for NaN/Inf in als_init */
+
+typedef struct {
+    int64_t n_u, n_m, nnz;
+    int32_t n_f;                 /* 1 <= n_f <= 64                            */
+    const int64_t *row_ptr;      /* CSR of R (users x items), device          */
+    const int32_t *col_idx;
+    const float *val;
+    double lambda;               /* >= 0; row i gets lambda * n_i on the diagonal */
+    uint32_t budget_num;         /* subsampling rate r = budget_num / budget_den,   */
+    uint32_t budget_den;         /* 0 < r <= 1; r = 1 is full-data ALS              */
+    int32_t min_keep;            /* s_i = min(n_i, max(min_keep, floor(n_i r)))     */
+    int32_t precision;           /* als_precision                                   */
+    uint32_t flags;              /* ALS_VALIDATE                                    */
+    void *stream;                /* hipStream_t                                     */
+    void *workspace;             /* device buffer, at least als_workspace_size bytes */
+    size_t workspace_bytes;
+} als_problem;
+
+typedef struct {
+    int64_t n_empty;             /* rows with no observed entry: output row is 0   */
+    int64_t n_singular_fallback; /* core systems with a pivot below n_f 2^-23 max|A|,
+                                    replaced by the full-data update eq. (U)      */
+    int64_t n_fp64_residual;     /* rows refined with an FP64 residual            */
+    int64_t n_rows;              /* rows solved in this half-sweep                */
+} als_sweep_stats;
+
+typedef struct {
+    double f;      /* objective of Section 2.1                                    */
+    double sse;    /* sum of squared residuals over I                              */
+    double rmse;   /* sqrt(sse / nnz)                                               */
+    double remse;  /* sqrt(sse) / sqrt(sum r^2)   (ReMSE, Section 5.1)              */
+} als_objective;
+
+/* Bytes of device workspace als_init needs for this problem (host only, no
+ * device call).  Returns 0 if the problem sizes are invalid. */
+size_t als_workspace_size(const als_problem *p);
+
+/* Validate R on the device, build its column view (CSC, rows ascending inside
+ * a column) in the workspace, compute degrees n_i, budgets s_i and the degree
+ * classes that schedule the half-sweeps.  The CSR arrays must stay alive and
+ * unchanged until als_destroy.  Syncs once.  Errors: ALS_E_ARG, ALS_E_INDEX,
+ * ALS_E_VALUE, ALS_E_NOMEM (workspace too small), ALS_E_DEVICE. */
+als_status als_init(const als_problem *p, als_ctx **out);
+
+/* Half-sweep over users (Algorithm 2, first loop; eq. core_ui): for every user
+ * i, X = rows of M indexed by the user's observed items, y = the user's
+ * ratings; CES on X, then U[i] = (X*^T X + lambda n_i E)^-1 X*^T y.
+ * M: [n_m * n_f] input; U: [n_u * n_f] output.  If st is non-NULL (host) the
+ * call syncs and fills the per-row event counts; otherwise it is fully
+ * asynchronous. */
+als_status half_sweep_users(als_ctx *c, const float *M, float *U, als_sweep_stats *st);
+
+/* Half-sweep over items (Algorithm 2, second loop; eq. core_mj), the same
+ * regression over the columns of R with U as the design side.
+ * U: [n_u * n_f] input; M: [n_m * n_f] output. */
+als_status half_sweep_items(als_ctx *c, const float *U, float *M, als_sweep_stats *st);
+
+/* Number of positions core_select writes for rows [row_begin, row_end) of one
+ * side: sum over rows of n_f * s_i.  side 0 = users (rows of R), 1 = items
+ * (columns of R).  *count is (host).  Syncs. */
+als_status core_select_count(als_ctx *c, int side, int64_t row_begin, int64_t row_end,
+                             int64_t *count);
+
+/* CES of Algorithm 1 for rows [row_begin, row_end) of one side, with `other`
+ * the opposite factor matrix (M for side 0, U for side 1).
+ * sel_ptr: [row_end - row_begin + 1] int64 output, sel_ptr[t] = offset of
+ * row row_begin + t.  sel_pos: output of capacity sel_cap int32; row t,
+ * column a occupies sel_pos[sel_ptr[t] + a*s .. + s), the s kept positions
+ * (0-based offsets into the row's observed entries) in ascending order.
+ * Ties in |x| keep the smaller position.  ALS_E_NOMEM if sel_cap is below
+ * core_select_count.  Asynchronous. */
+als_status core_select(als_ctx *c, int side, const float *other, int64_t row_begin,
+                       int64_t row_end, int64_t *sel_ptr, int32_t *sel_pos, int64_t sel_cap);
+
+/* Objective of Section 2.1 at (U, M), with SSE, RMSE and ReMSE (Section 5.1),
+ * accumulated in FP64 in a fixed order (deterministic).  out is (host).  Syncs. */
+als_status objective(als_ctx *c, const float *U, const float *M, als_objective *out);
+
+/* Release the context (host memory only; the caller frees its buffers). */
+void als_destroy(als_ctx *c);
+
+/* Message of the last failure on c (or of the last failed als_init when c is
+ * NULL).  Valid until the next call on the same context. */
+const char *als_last_error(const als_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORE_ALS_H */

@@ -1,0 +1,125 @@
+"""Torch-facing wrapper around the C ABI: holds device tensors and the context.
+
+Only marshalling happens here (shape/dtype/device checks, pointer passing);
+all computation runs in libcoreals.so.  The ALS driver alternates the two
+half-sweeps in the order of Algorithm 2 (users from M, then items from U).
+"""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+import torch
+
+from . import capi
+
+
+def _need(t: torch.Tensor, dtype, numel: Optional[int], name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+class CoreALS:
+    """One problem instance on the current CUDA (HIP) device."""
+
+    def __init__(self, n_u: int, n_m: int, n_f: int, row_ptr: torch.Tensor, col_idx: torch.Tensor,
+                 val: torch.Tensor, lam: float, budget: Tuple[int, int] = (1, 1), min_keep: int = 1,
+                 precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None):
+        capi.load()
+        nnz = int(col_idx.numel())
+        _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
+        _need(col_idx, torch.int32, None, "col_idx")
+        _need(val, torch.float32, nnz, "val")
+        self.n_u, self.n_m, self.n_f, self.nnz = int(n_u), int(n_m), int(n_f), nnz
+        self.device = row_ptr.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = (row_ptr, col_idx, val)
+        p = capi.als_problem()
+        p.n_u, p.n_m, p.nnz, p.n_f = self.n_u, self.n_m, nnz, self.n_f
+        p.row_ptr, p.col_idx, p.val = row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr()
+        p.lambda_ = float(lam)
+        p.budget_num, p.budget_den = int(budget[0]), int(budget[1])
+        p.min_keep = int(min_keep)
+        p.precision = int(precision)
+        p.flags = capi.ALS_VALIDATE if validate else 0
+        p.stream = self.stream.cuda_stream
+        size = capi.als_workspace_size(p)
+        if size == 0:
+            raise capi.ALSError(capi.ALS_E_ARG, "invalid problem sizes")
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        p.workspace, p.workspace_bytes = self.workspace.data_ptr(), size
+        self.problem = p
+        self.ctx = capi.als_init(p)
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda", budget=None, precision=capi.ALS_PREC_FP32, **kw):
+        rp = torch.as_tensor(prob.row_ptr, dtype=torch.int64).to(device)
+        ci = torch.as_tensor(prob.col_idx, dtype=torch.int32).to(device)
+        v = torch.as_tensor(prob.val, dtype=torch.float32).to(device)
+        b = budget if budget is not None else (prob.budget_num, prob.budget_den)
+        return cls(prob.n_u, prob.n_m, prob.n_f, rp, ci, v, prob.lam, b, prob.min_keep, precision, **kw)
+
+    def half_sweep_users(self, M: torch.Tensor, U: Optional[torch.Tensor] = None, stats: bool = False):
+        _need(M, torch.float32, self.n_m * self.n_f, "M")
+        if U is None:
+            U = torch.empty(self.n_u, self.n_f, dtype=torch.float32, device=self.device)
+        _need(U, torch.float32, self.n_u * self.n_f, "U")
+        st = capi.half_sweep_users(self.ctx, M.data_ptr(), U.data_ptr(), stats)
+        return (U, st) if stats else U
+
+    def half_sweep_items(self, U: torch.Tensor, M: Optional[torch.Tensor] = None, stats: bool = False):
+        _need(U, torch.float32, self.n_u * self.n_f, "U")
+        if M is None:
+            M = torch.empty(self.n_m, self.n_f, dtype=torch.float32, device=self.device)
+        _need(M, torch.float32, self.n_m * self.n_f, "M")
+        st = capi.half_sweep_items(self.ctx, U.data_ptr(), M.data_ptr(), stats)
+        return (M, st) if stats else M
+
+    def core_select(self, side: int, other: torch.Tensor, row_begin: int, row_end: int):
+        n_other = self.n_m if side == 0 else self.n_u
+        _need(other, torch.float32, n_other * self.n_f, "other")
+        cnt = capi.core_select_count(self.ctx, side, row_begin, row_end)
+        sel_ptr = torch.empty(row_end - row_begin + 1, dtype=torch.int64, device=self.device)
+        sel_pos = torch.empty(max(cnt, 1), dtype=torch.int32, device=self.device)
+        capi.core_select(self.ctx, side, other.data_ptr(), row_begin, row_end, sel_ptr.data_ptr(),
+                         sel_pos.data_ptr(), cnt)
+        return sel_ptr, sel_pos[:cnt]
+
+    def objective(self, U: torch.Tensor, M: torch.Tensor) -> dict:
+        _need(U, torch.float32, self.n_u * self.n_f, "U")
+        _need(M, torch.float32, self.n_m * self.n_f, "M")
+        o = capi.objective(self.ctx, U.data_ptr(), M.data_ptr())
+        return {"f": o.f, "sse": o.sse, "rmse": o.rmse, "remse": o.remse}
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            capi.als_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_als(als: CoreALS, M0: torch.Tensor, iters: int, record: bool = False):
+    """Algorithm 2: for t = 1..iters, U <- users(M), M <- items(U)."""
+    M = M0.clone()
+    U = torch.empty(als.n_u, als.n_f, dtype=torch.float32, device=als.device)
+    hist = []
+    for _ in range(iters):
+        als.half_sweep_users(M, U)
+        if record:
+            hist.append(als.objective(U, M))
+        als.half_sweep_items(U, M)
+        if record:
+            hist.append(als.objective(U, M))
+    return U, M, hist

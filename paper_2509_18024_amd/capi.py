@@ -1,0 +1,143 @@
+"""ctypes binding of libcoreals.so (include/coreals.h), same names as the C ABI.
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch is
+used for device memory (tensors whose data pointers are passed through) and
+for the stream handle.  Importing this module never falls back to anything:
+if the library is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcoreals.so")
+
+ALS_OK, ALS_E_ARG, ALS_E_INDEX, ALS_E_VALUE, ALS_E_NOMEM, ALS_E_DEVICE, ALS_E_STATE = range(7)
+ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES = 0, 1, 2
+ALS_VALIDATE = 1
+
+STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
+                5: "ALS_E_DEVICE", 6: "ALS_E_STATE"}
+
+
+class als_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_u", ctypes.c_int64), ("n_m", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("n_f", ctypes.c_int32),
+        ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p),
+        ("lambda_", ctypes.c_double),
+        ("budget_num", ctypes.c_uint32), ("budget_den", ctypes.c_uint32),
+        ("min_keep", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class als_sweep_stats(ctypes.Structure):
+    _fields_ = [("n_empty", ctypes.c_int64), ("n_singular_fallback", ctypes.c_int64),
+                ("n_fp64_residual", ctypes.c_int64), ("n_rows", ctypes.c_int64)]
+
+
+class als_objective(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_double), ("sse", ctypes.c_double), ("rmse", ctypes.c_double),
+                ("remse", ctypes.c_double)]
+
+
+class ALSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_items",
+           "core_select_count", "core_select", "objective", "als_destroy", "als_last_error"]
+
+
+def load():
+    """Load libcoreals.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or python paper_2509_18024_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.als_workspace_size.restype = ctypes.c_size_t
+    L.als_workspace_size.argtypes = [ctypes.POINTER(als_problem)]
+    L.als_init.restype = i32
+    L.als_init.argtypes = [ctypes.POINTER(als_problem), ctypes.POINTER(vp)]
+    for name in ("half_sweep_users", "half_sweep_items"):
+        f = getattr(L, name)
+        f.restype = i32
+        f.argtypes = [vp, vp, vp, ctypes.POINTER(als_sweep_stats)]
+    L.core_select_count.restype = i32
+    L.core_select_count.argtypes = [vp, i32, i64, i64, ctypes.POINTER(ctypes.c_int64)]
+    L.core_select.restype = i32
+    L.core_select.argtypes = [vp, i32, vp, i64, i64, vp, vp, i64]
+    L.objective.restype = i32
+    L.objective.argtypes = [vp, vp, vp, ctypes.POINTER(als_objective)]
+    L.als_destroy.restype = None
+    L.als_destroy.argtypes = [vp]
+    L.als_last_error.restype = ctypes.c_char_p
+    L.als_last_error.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _check(status: int, ctx) -> None:
+    if status != ALS_OK:
+        msg = load().als_last_error(ctx)
+        raise ALSError(status, msg.decode() if msg else "")
+
+
+def als_workspace_size(p: als_problem) -> int:
+    return int(load().als_workspace_size(ctypes.byref(p)))
+
+
+def als_init(p: als_problem):
+    ctx = ctypes.c_void_p()
+    _check(load().als_init(ctypes.byref(p), ctypes.byref(ctx)), None)
+    return ctx
+
+
+def half_sweep_users(ctx, M_ptr: int, U_ptr: int, stats: bool = False):
+    st = als_sweep_stats() if stats else None
+    _check(load().half_sweep_users(ctx, M_ptr, U_ptr, ctypes.byref(st) if st else None), ctx)
+    return st
+
+
+def half_sweep_items(ctx, U_ptr: int, M_ptr: int, stats: bool = False):
+    st = als_sweep_stats() if stats else None
+    _check(load().half_sweep_items(ctx, U_ptr, M_ptr, ctypes.byref(st) if st else None), ctx)
+    return st
+
+
+def core_select_count(ctx, side: int, row_begin: int, row_end: int) -> int:
+    out = ctypes.c_int64()
+    _check(load().core_select_count(ctx, side, row_begin, row_end, ctypes.byref(out)), ctx)
+    return int(out.value)
+
+
+def core_select(ctx, side: int, other_ptr: int, row_begin: int, row_end: int, sel_ptr_ptr: int,
+                sel_pos_ptr: int, sel_cap: int) -> None:
+    _check(load().core_select(ctx, side, other_ptr, row_begin, row_end, sel_ptr_ptr, sel_pos_ptr,
+                              sel_cap), ctx)
+
+
+def objective(ctx, U_ptr: int, M_ptr: int) -> als_objective:
+    out = als_objective()
+    _check(load().objective(ctx, U_ptr, M_ptr, ctypes.byref(out)), ctx)
+    return out
+
+
+def als_destroy(ctx) -> None:
+    load().als_destroy(ctx)
+
+
+def als_last_error(ctx) -> str:
+    m = load().als_last_error(ctx)
+    return m.decode() if m else ""

@@ -1,0 +1,275 @@
+"""Parity of the HIP library against the FP64 oracle (GPU), plus CPU checks
+that the built library exports every entry point the header declares.
+
+Tolerances: factors within 1e-4 relative Frobenius error of the oracle after
+one half-sweep from identical fp32 inputs; CES positions bit-exact.
+"""
+import os
+import re
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_18024_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "coreals.h")
+
+gpu = pytest.mark.gpu
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", txt, flags=re.M)))
+
+
+def test_header_symbols_exported():
+    """The built library exports every function include/coreals.h declares."""
+    import ctypes
+    from paper_2509_18024_amd import capi
+    if not os.path.exists(capi.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    names = header_functions()
+    assert set(capi.EXPORTS) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def rel_fro(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_als(prob, budget=None, **kw):
+    from paper_2509_18024_amd.als import CoreALS
+    return CoreALS.from_problem(prob, "cuda", budget=budget, **kw)
+
+
+def problems():
+    """Small problems covering every degree class, ties and padding of n_f."""
+    out = []
+    p = synth.random_problem(1, 60, 40, 8, 0.3, budget=(1, 4), heavy_rows=(0, 1))
+    out.append(("rand_nf8_r1/4", p))
+    p = synth.random_problem(2, 300, 500, 64, 0.08, budget=(1, 10), heavy_rows=(3, 7, 11))
+    out.append(("rand_nf64_r1/10", p))
+    p = synth.random_problem(3, 200, 900, 64, 0.2, budget=(1, 2), heavy_rows=(5,))
+    out.append(("rand_nf64_r1/2", p))
+    p = synth.random_problem(4, 150, 120, 32, 0.3, budget=(1, 1))
+    out.append(("rand_nf32_full", p))
+    p = synth.random_problem(5, 100, 400, 64, 0.15, budget=(3, 10), min_keep=0)
+    out.append(("rand_nf64_minkeep0", p))
+    return out
+
+
+def tie_problem():
+    """Factor values drawn from a small pool: many exact ties in |x|."""
+    p = synth.random_problem(6, 80, 300, 64, 0.25, budget=(1, 5), heavy_rows=(2,))
+    rng = np.random.default_rng(66)
+    pool = np.array([0.0, -0.0, 0.5, -0.5, 0.25, 1.0, -1.0, 2.0, 1e-40], np.float32)
+    p.M0 = rng.choice(pool, size=p.M0.shape).astype(np.float32)
+    return p
+
+
+@gpu
+@pytest.mark.parametrize("which", range(6))
+def test_core_select_bit_exact(ora, which):
+    import torch
+    probs = problems() + [("ties", tie_problem())]
+    name, p = probs[which]
+    note(f"[core_select] {name} n_u={p.n_u} n_m={p.n_m} n_f={p.n_f} r={p.budget_num}/{p.budget_den}")
+    als = make_als(p)
+    M = torch.from_numpy(p.M0).cuda()
+    sel_ptr, sel = als.core_select(0, M, 0, p.n_u)
+    torch.cuda.synchronize()
+    rows = np.arange(p.n_u)
+    rp, rs = ora.core_select_rows(rows, p.row_ptr, p.col_idx, p.M0.astype(np.float64),
+                                  p.budget_num, p.budget_den, p.min_keep)
+    assert np.array_equal(sel_ptr.cpu().numpy(), rp)
+    assert np.array_equal(sel.cpu().numpy(), rs)
+    als.close()
+
+
+@gpu
+def test_core_select_ties_and_item_side(ora):
+    import torch
+    p = tie_problem()
+    note(f"[core_select ties] n_u={p.n_u} n_m={p.n_m}")
+    als = make_als(p)
+    M = torch.from_numpy(p.M0).cuda()
+    for side in (0, 1):
+        if side == 0:
+            other, rp_, ci_ = p.M0, p.row_ptr, p.col_idx
+            n_rows = p.n_u
+        else:
+            U = np.random.default_rng(9).choice(np.array([0.0, 0.5, -0.5, 1.0], np.float32),
+                                                size=(p.n_u, p.n_f)).astype(np.float32)
+            other = U
+            rp_, ci_, _ = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+            n_rows = p.n_m
+        sel_ptr, sel = als.core_select(side, torch.from_numpy(other).cuda(), 0, n_rows)
+        torch.cuda.synchronize()
+        rp, rs = ora.core_select_rows(np.arange(n_rows), rp_, ci_, other.astype(np.float64),
+                                      p.budget_num, p.budget_den, p.min_keep)
+        assert np.array_equal(sel_ptr.cpu().numpy(), rp)
+        assert np.array_equal(sel.cpu().numpy(), rs)
+    als.close()
+
+
+@gpu
+@pytest.mark.parametrize("which", range(5))
+def test_half_sweeps_match_oracle(ora, which):
+    import torch
+    name, p = problems()[which]
+    note(f"[half-sweep] {name} n_u={p.n_u} n_m={p.n_m} n_f={p.n_f} r={p.budget_num}/{p.budget_den}")
+    als = make_als(p)
+    M = torch.from_numpy(p.M0).cuda()
+    U, st = als.half_sweep_users(M, stats=True)
+    torch.cuda.synchronize()
+    Uo, sto = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), p.lam,
+                             p.budget_num, p.budget_den, p.min_keep)
+    err = rel_fro(U.cpu().numpy(), Uo)
+    note(f"  users rel err {err:.3e}  empty={st.n_empty} fallback={st.n_singular_fallback}")
+    assert err <= 1e-4
+    assert st.n_empty == sto[0]
+    # items from the oracle's own U (as fp32): identical inputs for both sides
+    U32 = Uo.astype(np.float32)
+    Mg, st2 = als.half_sweep_items(torch.from_numpy(U32).cuda(), stats=True)
+    torch.cuda.synchronize()
+    cp, ri, vt = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+    Mo, sto2 = ora.half_sweep(cp, ri, vt, U32.astype(np.float64), p.lam, p.budget_num,
+                              p.budget_den, p.min_keep)
+    err = rel_fro(Mg.cpu().numpy(), Mo)
+    note(f"  items rel err {err:.3e}  empty={st2.n_empty} fallback={st2.n_singular_fallback}")
+    assert err <= 1e-4
+    assert st2.n_empty == sto2[0]
+    als.close()
+
+
+@gpu
+def test_c1_plain_als_ten_iterations(ora):
+    """C1: plain full-data ALS, 10 iterations, FP32 GPU vs FP64 oracle."""
+    import torch
+    from paper_2509_18024_amd.als import run_als
+    p = synth.c1_plain()
+    note(f"[C1] nnz={p.nnz}")
+    als = make_als(p)
+    U, M, hist = run_als(als, torch.from_numpy(p.M0).cuda(), p.iters, record=True)
+    torch.cuda.synchronize()
+    Uo, Mo, ho = ora.als(p, iters=p.iters)
+    eu, em = rel_fro(U.cpu().numpy(), Uo), rel_fro(M.cpu().numpy(), Mo)
+    note(f"  U err {eu:.3e}  M err {em:.3e}  rmse gpu {hist[-1]['rmse']:.6f} oracle {ho[-1][2]:.6f}")
+    assert eu <= 1e-4 and em <= 1e-4
+    assert abs(hist[-1]["rmse"] - ho[-1][2]) <= 1e-5
+    f = [h["f"] for h in hist]
+    for a, b in zip(f, f[1:]):
+        assert b <= a * (1 + 1e-5)
+    als.close()
+
+
+@gpu
+def test_c2_core_rmse_gap_small_scale(ora):
+    """C2 recipe at 5% scale, r = 1/10, 15 iterations: RMSE gap <= 1e-3."""
+    import torch
+    from paper_2509_18024_amd.als import run_als
+    p = synth.c2_core(scale=0.05)
+    note(f"[C2 small] n_u={p.n_u} n_m={p.n_m} nnz={p.nnz}")
+    als = make_als(p)
+    U, M, hist = run_als(als, torch.from_numpy(p.M0).cuda(), p.iters, record=True)
+    torch.cuda.synchronize()
+    Uo, Mo, ho = ora.als(p, iters=p.iters, record=False)
+    ro = ora.objective(p.row_ptr, p.col_idx, p.val, Uo, Mo, p.lam)[2]
+    rg = hist[-1]["rmse"]
+    note(f"  rmse gpu {rg:.6f} oracle {ro:.6f} gap {abs(rg - ro):.2e}")
+    assert abs(rg - ro) <= 1e-3
+    als.close()
+
+
+@gpu
+def test_objective_matches_oracle(ora):
+    import torch
+    p = synth.random_problem(7, 200, 300, 64, 0.1)
+    note("[objective]")
+    als = make_als(p)
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal((p.n_u, p.n_f)).astype(np.float32)
+    M = rng.standard_normal((p.n_m, p.n_f)).astype(np.float32)
+    o = als.objective(torch.from_numpy(U).cuda(), torch.from_numpy(M).cuda())
+    f, sse, rmse, remse = ora.objective(p.row_ptr, p.col_idx, p.val, U, M, p.lam)
+    assert o["f"] == pytest.approx(f, rel=1e-5)
+    assert o["sse"] == pytest.approx(sse, rel=1e-5)
+    assert o["rmse"] == pytest.approx(rmse, rel=1e-5)
+    assert o["remse"] == pytest.approx(remse, rel=1e-5)
+    o2 = als.objective(torch.from_numpy(U).cuda(), torch.from_numpy(M).cuda())
+    assert o2 == o  # fixed reduction order: bit-identical
+    als.close()
+
+
+@gpu
+def test_empty_rows_and_singular_fallback(ora):
+    import torch
+    p = synth.random_problem(8, 50, 60, 4, 0.2, lam=0.0, budget=(1, 3))
+    # empty users 0..4, and a repeated item factor so that some core systems are singular
+    rp = p.row_ptr.copy()
+    counts = np.diff(rp)
+    counts[:5] = 0
+    keep = np.repeat(np.arange(p.n_u), np.diff(rp)) >= 5
+    ci = p.col_idx[keep]
+    v = p.val[keep]
+    rp2 = np.zeros_like(rp)
+    np.cumsum(counts, out=rp2[1:])
+    p = synth.Problem("empty_singular", p.n_u, p.n_m, p.n_f, rp2, ci, v, 0.0, 1, 3, 1, 1,
+                      np.tile(p.M0[:1], (p.n_m, 1)) + np.eye(p.n_m, p.n_f, dtype=np.float32) * 0.5)
+    note("[empty+singular]")
+    als = make_als(p)
+    U, st = als.half_sweep_users(torch.from_numpy(p.M0).cuda(), stats=True)
+    torch.cuda.synchronize()
+    Uo, sto = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), 0.0, 1, 3, 1)
+    note(f"  empty {st.n_empty}/{sto[0]} fallback {st.n_singular_fallback}/{sto[1]}")
+    assert st.n_empty == 5 and sto[0] == 5
+    assert np.all(U.cpu().numpy()[:5] == 0)
+    assert st.n_singular_fallback > 0
+    als.close()
+
+
+@gpu
+def test_validation_errors():
+    import torch
+    from paper_2509_18024_amd import capi
+    from paper_2509_18024_amd.als import CoreALS
+    rp = torch.tensor([0, 2, 3], dtype=torch.int64, device="cuda")
+    bad = torch.tensor([3, 0, 1], dtype=torch.int32, device="cuda")
+    v = torch.ones(3, dtype=torch.float32, device="cuda")
+    with pytest.raises(capi.ALSError) as ei:
+        CoreALS(2, 4, 8, rp, bad, v, 0.1)
+    assert ei.value.status == capi.ALS_E_INDEX
+    good = torch.tensor([0, 3, 1], dtype=torch.int32, device="cuda")
+    nan = torch.tensor([1.0, float("nan"), 1.0], dtype=torch.float32, device="cuda")
+    with pytest.raises(capi.ALSError) as ei:
+        CoreALS(2, 4, 8, rp, good, nan, 0.1)
+    assert ei.value.status == capi.ALS_E_VALUE
+    with pytest.raises(capi.ALSError) as ei:
+        CoreALS(2, 4, 8, rp, good, v, 0.1, budget=(0, 1))
+    assert ei.value.status == capi.ALS_E_ARG
+
+
+@gpu
+def test_deterministic_repeat():
+    import torch
+    p = synth.random_problem(9, 200, 300, 64, 0.1, budget=(1, 10), heavy_rows=(1,))
+    als = make_als(p)
+    M = torch.from_numpy(p.M0).cuda()
+    U1 = als.half_sweep_users(M).clone()
+    U2 = als.half_sweep_users(M).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    als.close()
