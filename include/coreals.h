@@ -73,6 +73,11 @@ typedef struct {
     void *stream;                /* hipStream_t                                     */
     void *workspace;             /* device buffer, at least als_workspace_size bytes */
     size_t workspace_bytes;
+    int32_t heavy_min_degree;    /* schedule: rows of higher degree (or budget > 32)
+                                    are split across workgroups; 0 = default 1024 */
+    int32_t heavy_chunk;         /* entries per partial Gram of such rows; 0 = 1024 */
+    int32_t heavy_pair_cap;      /* partial systems kept in scratch at once (sizes the
+                                    workspace); 0 = 32768 */
 } als_problem;
 
 typedef struct {
@@ -134,6 +139,21 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
 /* Objective of Section 2.1 at (U, M), with SSE, RMSE and ReMSE (Section 5.1),
  * accumulated in FP64 in a fixed order (deterministic).  out is (host).  Syncs. */
 als_status objective(als_ctx *c, const float *U, const float *M, als_objective *out);
+
+/* Kernel timing for measurement.  After als_profile_begin, every half-sweep
+ * records a pair of HIP events around each kernel (group) it launches (on the
+ * problem's stream; no synchronisation is added).  als_profile_end syncs and
+ * fills (host) ms[side*10 + k] with the summed time and launches[side*10 + k]
+ * with the number of launches since als_profile_begin.  side 0 = users,
+ * 1 = items; k = 0: light full-data rows, 1..6: light rows with insertion
+ * networks of capacity 1, 2, 4, 8, 16, 32, 7: heavy-row selection, 8: heavy-row
+ * Gram chunks, 9: heavy-row solves.  Either array may be NULL.  Profiling then
+ * stops. */
+als_status als_profile_begin(als_ctx *c);
+als_status als_profile_end(als_ctx *c, double *ms, int64_t *launches);
+
+/* Row counts of the degree classes (host out[side*8 + cls]); no device call. */
+als_status als_class_counts(const als_ctx *c, int64_t *out);
 
 /* Release the context (host memory only; the caller frees its buffers). */
 void als_destroy(als_ctx *c);

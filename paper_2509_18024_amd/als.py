@@ -31,7 +31,8 @@ class CoreALS:
 
     def __init__(self, n_u: int, n_m: int, n_f: int, row_ptr: torch.Tensor, col_idx: torch.Tensor,
                  val: torch.Tensor, lam: float, budget: Tuple[int, int] = (1, 1), min_keep: int = 1,
-                 precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None):
+                 precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
+                 heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -50,6 +51,9 @@ class CoreALS:
         p.precision = int(precision)
         p.flags = capi.ALS_VALIDATE if validate else 0
         p.stream = self.stream.cuda_stream
+        p.heavy_min_degree = int(heavy_min_degree)
+        p.heavy_chunk = int(heavy_chunk)
+        p.heavy_pair_cap = int(heavy_pair_cap)
         size = capi.als_workspace_size(p)
         if size == 0:
             raise capi.ALSError(capi.ALS_E_ARG, "invalid problem sizes")

@@ -31,6 +31,8 @@ class als_problem(ctypes.Structure):
         ("min_keep", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+        ("heavy_min_degree", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
+        ("heavy_pair_cap", ctypes.c_int32),
     ]
 
 
@@ -53,7 +55,13 @@ class ALSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_items",
-           "core_select_count", "core_select", "objective", "als_destroy", "als_last_error"]
+           "core_select_count", "core_select", "objective", "als_profile_begin", "als_profile_end",
+           "als_class_counts", "als_destroy", "als_last_error"]
+NCLASS = 8
+CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
+NPROF = 10
+PROF_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy_select", "heavy_gram",
+              "heavy_solve"]
 
 
 def load():
@@ -80,6 +88,12 @@ def load():
     L.core_select.argtypes = [vp, i32, vp, i64, i64, vp, vp, i64]
     L.objective.restype = i32
     L.objective.argtypes = [vp, vp, vp, ctypes.POINTER(als_objective)]
+    L.als_profile_begin.restype = i32
+    L.als_profile_begin.argtypes = [vp]
+    L.als_profile_end.restype = i32
+    L.als_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.als_class_counts.restype = i32
+    L.als_class_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.als_destroy.restype = None
     L.als_destroy.argtypes = [vp]
     L.als_last_error.restype = ctypes.c_char_p
@@ -132,6 +146,24 @@ def objective(ctx, U_ptr: int, M_ptr: int) -> als_objective:
     out = als_objective()
     _check(load().objective(ctx, U_ptr, M_ptr, ctypes.byref(out)), ctx)
     return out
+
+
+def als_profile_begin(ctx) -> None:
+    _check(load().als_profile_begin(ctx), ctx)
+
+
+def als_profile_end(ctx):
+    """Returns (ms[2][NPROF], launches[2][NPROF]) summed since als_profile_begin."""
+    ms = (ctypes.c_double * (2 * NPROF))()
+    n = (ctypes.c_int64 * (2 * NPROF))()
+    _check(load().als_profile_end(ctx, ms, n), ctx)
+    return ([list(ms[:NPROF]), list(ms[NPROF:])], [list(n[:NPROF]), list(n[NPROF:])])
+
+
+def als_class_counts(ctx):
+    out = (ctypes.c_int64 * (2 * NCLASS))()
+    _check(load().als_class_counts(ctx, out), ctx)
+    return [list(out[:NCLASS]), list(out[NCLASS:])]
 
 
 def als_destroy(ctx) -> None:

@@ -1,9 +1,11 @@
 // C ABI of the core-elements ALS library: argument checks, workspace carving,
 // setup (validation, CSC, schedules) and the half-sweep / selection /
 // objective entry points declared in include/coreals.h.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -40,10 +42,39 @@ struct Layout {
     int *err_flags;
     double *obj_partials;
     double *obj_out;
+    float *partials;
+    struct SideArrays {
+        int32_t *pair_slot, *pair_chunk, *cutT, *cutK;
+        int64_t *pair_off;
+    } side[2];
     void *temp;
     size_t temp_bytes;
     size_t total;
 };
+
+int32_t heavy_n_of(const als_problem &p) {
+    int32_t h = p.heavy_min_degree > 0 ? p.heavy_min_degree : DEFAULT_HEAVY_N;
+    return h < 64 ? 64 : h;
+}
+
+int64_t pair_cap_of(const als_problem &p) {
+    return p.heavy_pair_cap > 0 ? std::min<int64_t>(p.heavy_pair_cap, PAIR_CAP) : PAIR_CAP;
+}
+
+int32_t chunk_of(const als_problem &p) {
+    int32_t c = p.heavy_chunk > 0 ? p.heavy_chunk : DEFAULT_CHUNK;
+    return c < CK ? CK : c;
+}
+
+// Heavy rows have s > 32 or degree > heavy_n >= 64, so there are at most
+// nnz / 33 of them; their chunk pairs number at most nnz / chunk + n_heavy.
+int64_t heavy_bound(const als_problem &p, int64_t n_rows) {
+    return std::min<int64_t>(n_rows, p.nnz / 33 + 1);
+}
+
+int64_t pair_bound(const als_problem &p, int64_t n_rows) {
+    return p.nnz / chunk_of(p) + heavy_bound(p, n_rows) + 1;
+}
 
 Layout carve(const als_problem &p, void *base) {
     Carve c{reinterpret_cast<char *>(base), 0, 0};
@@ -59,6 +90,16 @@ Layout carve(const als_problem &p, void *base) {
     L.err_flags = c.take<int>(4);
     L.obj_partials = c.take<double>((size_t)5 * objective_blocks());
     L.obj_out = c.take<double>(4);
+    L.partials = c.take<float>((size_t)pair_cap_of(p) * (NF + 1) * 64);
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t nr = sd == 0 ? p.n_u : p.n_m;
+        const int64_t hb = heavy_bound(p, nr), pb = pair_bound(p, nr);
+        L.side[sd].pair_slot = c.take<int32_t>((size_t)pb);
+        L.side[sd].pair_chunk = c.take<int32_t>((size_t)pb);
+        L.side[sd].pair_off = c.take<int64_t>((size_t)hb + 1);
+        L.side[sd].cutT = c.take<int32_t>((size_t)hb * 64);
+        L.side[sd].cutK = c.take<int32_t>((size_t)hb * 64);
+    }
     size_t tb = csc_temp_bytes(p.nnz, p.n_m);
     size_t tp = perm_temp_bytes(p.n_u > p.n_m ? p.n_u : p.n_m);
     L.temp_bytes = tb > tp ? tb : tp;
@@ -95,7 +136,22 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
     if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
     const Side &S = c->side[side];
     HIP_CHECK(c, hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * NSTATS, c->stream));
-    for (int cls = 0; cls < NCLASS; ++cls) {
+    auto mark_begin = [&](int cls, als_ctx::Mark &mk) -> hipError_t {
+        if (!c->profiling) return hipSuccess;
+        hipError_t e = hipEventCreate(&mk.start);
+        if (e == hipSuccess) e = hipEventCreate(&mk.stop);
+        mk.side = side;
+        mk.cls = cls;
+        if (e == hipSuccess) e = hipEventRecord(mk.start, c->stream);
+        return e;
+    };
+    auto mark_end = [&](als_ctx::Mark &mk) -> hipError_t {
+        if (!c->profiling) return hipSuccess;
+        hipError_t e = hipEventRecord(mk.stop, c->stream);
+        c->marks.push_back(mk);
+        return e;
+    };
+    for (int cls = 0; cls < CLS_HEAVY; ++cls) {
         SweepArgs a;
         a.ptr = S.ptr;
         a.idx = S.idx;
@@ -110,7 +166,51 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         a.den = c->p.budget_den;
         a.min_keep = c->p.min_keep;
         a.stats = c->stats;
+        if (a.count <= 0) continue;
+        als_ctx::Mark mk{};
+        HIP_CHECK(c, mark_begin(cls, mk));
         HIP_CHECK(c, launch_sweep_class(cls, a, c->stream));
+        HIP_CHECK(c, mark_end(mk));
+    }
+    const HeavyPlan &H = S.heavy;
+    if (H.n_heavy > 0) {
+        HeavyArgs h;
+        h.ptr = S.ptr;
+        h.idx = S.idx;
+        h.val = S.val;
+        h.other = other;
+        h.out = out;
+        h.rows = S.perm + S.class_off[CLS_HEAVY];
+        h.count = H.n_heavy;
+        h.nf = c->p.n_f;
+        h.lam = (float)c->p.lambda;
+        h.num = c->p.budget_num;
+        h.den = c->p.budget_den;
+        h.min_keep = c->p.min_keep;
+        h.heavy_n = c->heavy_n;
+        h.chunk = c->chunk;
+        h.pair_slot = H.pair_slot;
+        h.pair_chunk = H.pair_chunk;
+        h.pair_off = H.pair_off;
+        h.cutT = H.cutT;
+        h.cutK = H.cutK;
+        h.partials = c->partials;
+        h.stats = c->stats;
+        if (c->p.budget_num < c->p.budget_den) {
+            als_ctx::Mark mk{};
+            HIP_CHECK(c, mark_begin(PROF_HSELECT, mk));
+            HIP_CHECK(c, launch_heavy_select(h, 0, c->stream));
+            HIP_CHECK(c, mark_end(mk));
+        }
+        for (const auto &b : H.batches) {
+            als_ctx::Mark mg{}, ms{};
+            HIP_CHECK(c, mark_begin(PROF_HGRAM, mg));
+            HIP_CHECK(c, launch_heavy_gram(h, b.pair_begin, b.pair_end, c->stream));
+            HIP_CHECK(c, mark_end(mg));
+            HIP_CHECK(c, mark_begin(PROF_HSOLVE, ms));
+            HIP_CHECK(c, launch_heavy_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+            HIP_CHECK(c, mark_end(ms));
+        }
     }
     if (st) {
         unsigned long long h[NSTATS];
@@ -160,6 +260,10 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->stats = L.stats;
     c->obj_partials = L.obj_partials;
     c->obj_out = L.obj_out;
+    c->partials = L.partials;
+    c->heavy_n = heavy_n_of(*p);
+    c->chunk = chunk_of(*p);
+    c->pair_cap = pair_cap_of(*p);
     c->temp = L.temp;
     c->temp_bytes = L.temp_bytes;
 
@@ -209,7 +313,7 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     int64_t host_max[2];
     for (int sd = 0; sd < 2; ++sd) {
         Side &S = c->side[sd];
-        INIT_HIP(build_schedule(S.n_rows, S.ptr, p->budget_num, p->budget_den, p->min_keep, S.perm,
+        INIT_HIP(build_schedule(S.n_rows, S.ptr, p->budget_num, p->budget_den, p->min_keep, c->heavy_n, S.perm,
                                 L.class_count + sd * NCLASS, L.max_deg + sd, L.temp, s));
     }
     INIT_HIP(hipMemcpyAsync(host_counts, L.class_count, sizeof(host_counts), hipMemcpyDeviceToHost, s));
@@ -220,6 +324,54 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         S.class_off[0] = 0;
         for (int k = 0; k < NCLASS; ++k) S.class_off[k + 1] = S.class_off[k] + host_counts[sd * NCLASS + k];
         S.max_deg = host_max[sd];
+    }
+    // heavy-row plan: chunk pairs and batches that fit the partial scratch
+    for (int sd = 0; sd < 2; ++sd) {
+        Side &S = c->side[sd];
+        HeavyPlan &H = S.heavy;
+        H.n_heavy = S.class_off[CLS_HEAVY + 1] - S.class_off[CLS_HEAVY];
+        H.pair_slot = L.side[sd].pair_slot;
+        H.pair_chunk = L.side[sd].pair_chunk;
+        H.pair_off = L.side[sd].pair_off;
+        H.cutT = L.side[sd].cutT;
+        H.cutK = L.side[sd].cutK;
+        if (H.n_heavy == 0) continue;
+        if (H.n_heavy > heavy_bound(*p, S.n_rows)) return bail(ALS_E_STATE, "heavy-row bound violated");
+        std::vector<int32_t> rows((size_t)H.n_heavy);
+        std::vector<int64_t> ptr((size_t)S.n_rows + 1);
+        INIT_HIP(hipMemcpyAsync(rows.data(), S.perm + S.class_off[CLS_HEAVY], sizeof(int32_t) * rows.size(),
+                                hipMemcpyDeviceToHost, s));
+        INIT_HIP(hipMemcpyAsync(ptr.data(), S.ptr, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, s));
+        INIT_HIP(hipStreamSynchronize(s));
+        std::vector<int64_t> off((size_t)H.n_heavy + 1, 0);
+        for (int64_t t = 0; t < H.n_heavy; ++t) {
+            const int64_t n = ptr[rows[t] + 1] - ptr[rows[t]];
+            const int64_t chunks = std::max<int64_t>(1, (n + c->chunk - 1) / c->chunk);
+            off[t + 1] = off[t] + chunks;
+        }
+        H.n_pairs = off[H.n_heavy];
+        if (H.n_pairs > pair_bound(*p, S.n_rows)) return bail(ALS_E_STATE, "pair bound violated");
+        std::vector<int32_t> pslot((size_t)H.n_pairs), pchunk((size_t)H.n_pairs);
+        for (int64_t t = 0; t < H.n_heavy; ++t)
+            for (int64_t q = off[t]; q < off[t + 1]; ++q) {
+                pslot[q] = (int32_t)t;
+                pchunk[q] = (int32_t)(q - off[t]);
+            }
+        H.batches.clear();
+        int64_t t0 = 0;
+        while (t0 < H.n_heavy) {
+            int64_t t1 = t0 + 1;
+            while (t1 < H.n_heavy && off[t1 + 1] - off[t0] <= c->pair_cap) ++t1;
+            if (off[t1] - off[t0] > c->pair_cap)
+                return bail(ALS_E_NOMEM, "a heavy row needs more partial systems than heavy_pair_cap");
+            H.batches.push_back({t0, t1, off[t0], off[t1]});
+            t0 = t1;
+        }
+        INIT_HIP(hipMemcpyAsync(H.pair_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, s));
+        INIT_HIP(hipMemcpyAsync(H.pair_slot, pslot.data(), sizeof(int32_t) * pslot.size(), hipMemcpyHostToDevice, s));
+        INIT_HIP(hipMemcpyAsync(H.pair_chunk, pchunk.data(), sizeof(int32_t) * pchunk.size(), hipMemcpyHostToDevice,
+                                s));
+        INIT_HIP(hipStreamSynchronize(s));
     }
 #undef INIT_HIP
     *out = c;
@@ -264,19 +416,44 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
                                 c->stream));
     HIP_CHECK(c, hipStreamSynchronize(c->stream));
     if (total > sel_cap) return fail(c, ALS_E_NOMEM, "sel_pos capacity below core_select_count%s");
-    SelectArgs a;
-    a.ptr = S.ptr;
-    a.idx = S.idx;
-    a.other = other;
-    a.row_begin = row_begin;
-    a.row_end = row_end;
-    a.nf = c->p.n_f;
-    a.num = c->p.budget_num;
-    a.den = c->p.budget_den;
-    a.min_keep = c->p.min_keep;
-    a.sel_ptr = sel_ptr;
-    a.sel_pos = sel_pos;
-    HIP_CHECK(c, launch_select(a, c->stream));
+    // heavy rows of the range: cuts by the sweep's own heavy-row selection,
+    // stored in the partial scratch, processed in sub-ranges that fit it
+    const int64_t sub = c->pair_cap * (NF + 1) * 64 / 128;
+    for (int64_t r0 = row_begin; r0 < row_end; r0 += sub) {
+        const int64_t r1 = std::min(row_end, r0 + sub);
+        int32_t *cutT = reinterpret_cast<int32_t *>(c->partials);
+        int32_t *cutK = cutT + (r1 - r0) * 64;
+        HeavyArgs h{};
+        h.ptr = S.ptr;
+        h.idx = S.idx;
+        h.other = other;
+        h.rows = nullptr;
+        h.count = r1 - r0;
+        h.nf = c->p.n_f;
+        h.num = c->p.budget_num;
+        h.den = c->p.budget_den;
+        h.min_keep = c->p.min_keep;
+        h.heavy_n = c->heavy_n;
+        h.cutT = cutT;
+        h.cutK = cutK;
+        HIP_CHECK(c, launch_heavy_select(h, r0, c->stream));
+        SelectArgs a;
+        a.ptr = S.ptr;
+        a.idx = S.idx;
+        a.other = other;
+        a.row_begin = r0;
+        a.row_end = r1;
+        a.nf = c->p.n_f;
+        a.num = c->p.budget_num;
+        a.den = c->p.budget_den;
+        a.min_keep = c->p.min_keep;
+        a.heavy_n = c->heavy_n;
+        a.sel_ptr = sel_ptr + (r0 - row_begin);
+        a.sel_pos = sel_pos;
+        a.cutT = cutT;
+        a.cutK = cutK;
+        HIP_CHECK(c, launch_select(a, c->stream));
+    }
     return ALS_OK;
 }
 
@@ -295,7 +472,52 @@ als_status objective(als_ctx *c, const float *U, const float *M, als_objective *
     return ALS_OK;
 }
 
-void als_destroy(als_ctx *c) { delete c; }
+als_status als_profile_begin(als_ctx *c) {
+    if (!c) return ALS_E_STATE;
+    for (auto &m : c->marks) {
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    c->marks.clear();
+    c->profiling = true;
+    return ALS_OK;
+}
+
+als_status als_profile_end(als_ctx *c, double *ms, int64_t *launches) {
+    if (!c) return ALS_E_STATE;
+    if (ms)
+        for (int k = 0; k < 2 * NPROF; ++k) ms[k] = 0.0;
+    if (launches)
+        for (int k = 0; k < 2 * NPROF; ++k) launches[k] = 0;
+    HIP_CHECK(c, hipStreamSynchronize(c->stream));
+    for (auto &m : c->marks) {
+        float t = 0.f;
+        HIP_CHECK(c, hipEventElapsedTime(&t, m.start, m.stop));
+        if (ms) ms[m.side * NPROF + m.cls] += t;
+        if (launches) launches[m.side * NPROF + m.cls] += 1;
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    c->marks.clear();
+    c->profiling = false;
+    return ALS_OK;
+}
+
+als_status als_class_counts(const als_ctx *c, int64_t *out) {
+    if (!c || !out) return ALS_E_STATE;
+    for (int sd = 0; sd < 2; ++sd)
+        for (int k = 0; k < NCLASS; ++k) out[sd * NCLASS + k] = c->side[sd].class_off[k + 1] - c->side[sd].class_off[k];
+    return ALS_OK;
+}
+
+void als_destroy(als_ctx *c) {
+    if (!c) return;
+    for (auto &m : c->marks) {
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    delete c;
+}
 
 const char *als_last_error(const als_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 

@@ -1,0 +1,376 @@
+// Heavy rows of a half-sweep (gfx950): rows whose budget exceeds the register
+// insertion networks (s > 32) or whose degree exceeds the light-row limit.
+//
+//   k_heavy_select  one 256-thread workgroup per row computes the CES cut of
+//                   all 64 columns (Algorithm 1): an MSD radix select on the
+//                   31-bit key |x|, 8 bits per pass, with per-column counters
+//                   packed two per 32-bit LDS word (degrees < 65536).  After two
+//                   passes (exponent byte, top mantissa byte) the few keys that
+//                   share the threshold's 16-bit prefix are copied into LDS and
+//                   ranked exactly by (key desc, position asc); only if more
+//                   than HEAVY_CAP keys share it do two more radix passes and
+//                   a position pass run.  Three gathers of the row in the
+//                   common case.
+//   k_heavy_gram    one wavefront per (row, chunk of `chunk` entries) builds
+//                   the chunk's part of X*^T X and X*^T y (eq. core_ui) with
+//                   the row's cut, and stores it to scratch (column-major, so
+//                   lane a writes row a of the system with coalesced stores).
+//   k_heavy_solve   one wavefront per row sums its partial systems in chunk
+//                   order (deterministic), adds lambda n_i, and solves it
+//                   (pivoted LU; LDL^T when s == n).
+#include "rowops.hpp"
+
+namespace coreals {
+
+namespace {
+
+constexpr int HS_THREADS = 256;
+constexpr int HS_WAVES = HS_THREADS / 64;
+
+struct HeavySelLds {
+    // Narrow rows (n < 65536): bins 2j, 2j+1 of column a share word [j][a] as
+    // two 16-bit counters.  Wide rows: word [d - dlo][a] is the 32-bit count of
+    // digit d within the half range [dlo, dlo + 128) being counted.
+    uint32_t hist[128][64];
+    int ckey[64][HEAVY_CAP];
+    int cpos[64][HEAVY_CAP];
+    int ccnt[64];
+    int prefix[64];
+    int rem[64];
+    int ceq[64];
+    int cum[64];
+    int found[64];
+    int done[64];
+    int T[64];
+    int K[64];
+    int flag;
+};
+
+__device__ __forceinline__ bool is_heavy_core(int n, int s, int heavy_n) {
+    return class_of(n, s, heavy_n) == CLS_HEAVY && s < n;
+}
+
+// The load is unconditional (lane clamped to a valid column) so that a run of
+// these gathers stays in flight together; padded lanes get key 0.
+__device__ __forceinline__ int heavy_key(const float *other, int col, int lane, int nf) {
+    const int k = key_of(other[(size_t)col * nf + min(lane, nf - 1)]);
+    return lane < nf ? k : 0;
+}
+
+// One counting pass over the row: for keys whose bits above `shift` equal the
+// column's prefix, count digit d = bits [shift, shift + width) if d lies in
+// [dlo, dhi).  Waves take interleaved chunks of 64 positions; lane a reads
+// column a (one 256-byte factor row per load instruction).
+__device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const float *other, int nf,
+                                                int64_t beg, int n, int shift, int width, int hmask, int dlo,
+                                                int dhi, bool wide, int w, int lane) {
+    const int pre = S.prefix[lane];
+    const bool act = !S.done[lane] && !S.found[lane];
+    const int dmask = (1 << width) - 1;
+    for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
+        const int m = min(64, n - c0);
+        const int colv = lane < m ? idx[beg + c0 + lane] : 0;
+        // 16 gathers in flight per batch, then the 16 keys are counted
+        for (int j0 = 0; j0 < m; j0 += 16) {
+            int key[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                // positions past m read factor row colv = 0 (valid) and are dropped
+                const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
+                const int kk = heavy_key(other, col, lane, nf);
+                key[j] = (j0 + j < m) ? kk : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
+                    const int d = (key[j] >> shift) & dmask;
+                    if (d >= dlo && d < dhi) {
+                        if (wide) atomicAdd(&S.hist[d - dlo][lane], 1u);
+                        else atomicAdd(&S.hist[d >> 1][lane], 1u << ((d & 1) << 4));
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Column a: walk digits dhi-1 .. dlo from the top; if the rem-th largest key
+// falls in this range, fix the digit, else carry the running count.
+__device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int dlo, int dhi, bool wide) {
+    if (S.done[a] || S.found[a]) return;
+    int cum = S.cum[a], dsel = -1, below = 0, hsel = 0;
+    const int rem = S.rem[a];
+    for (int d = dhi - 1; d >= dlo; --d) {
+        const int h = wide ? (int)S.hist[d - dlo][a] : (int)((S.hist[d >> 1][a] >> ((d & 1) << 4)) & 0xFFFFu);
+        if (cum < rem && cum + h >= rem) {
+            dsel = d;
+            below = cum;
+            hsel = h;
+        }
+        cum += h;
+    }
+    if (dsel < 0) {
+        S.cum[a] = cum;
+        return;
+    }
+    S.found[a] = 1;
+    S.rem[a] = rem - below;
+    S.prefix[a] |= dsel << shift;
+    S.ceq[a] = hsel;
+    if (hsel == S.rem[a]) {  // every key with this prefix is kept
+        S.done[a] = 1;
+        S.T[a] = S.prefix[a];
+        S.K[a] = 0x7FFFFFFF;
+    }
+}
+
+__global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_t row_begin) {
+    __shared__ HeavySelLds S;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int nf = a.nf;
+    for (int64_t t = blockIdx.x; t < a.count; t += gridDim.x) {
+        const int64_t i = a.rows ? (int64_t)a.rows[t] : row_begin + t;
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        if (!is_heavy_core(n, s, a.heavy_n)) continue;  // uniform over the workgroup
+        const bool wide = n >= 65536;
+        if (tid < 64) {
+            S.prefix[tid] = 0;
+            S.rem[tid] = s;
+            S.done[tid] = 0;
+            S.ccnt[tid] = 0;
+            S.T[tid] = 0;
+            S.K[tid] = 0x7FFFFFFF;
+        }
+        int hmask = 0;
+        bool collected = false, all_done = false;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = pass < 3 ? 23 - 8 * pass : 0;
+            const int width = pass < 3 ? 8 : 7;
+            const int nd = 1 << width;
+            if (tid < 64) {
+                S.cum[tid] = 0;
+                S.found[tid] = 0;
+            }
+            // narrow rows: one sub-pass over all digits; wide rows: upper half
+            // first, the lower half only for columns not yet resolved
+            const int nsub = wide ? 2 : 1;
+            for (int sub = 0; sub < nsub; ++sub) {
+                const int dlo = wide ? (sub == 0 ? nd / 2 : 0) : 0;
+                const int dhi = wide ? (sub == 0 ? nd : nd / 2) : nd;
+                for (int q = tid; q < 128 * 64; q += HS_THREADS) (&S.hist[0][0])[q] = 0u;
+                __syncthreads();
+                heavy_hist_pass(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, wide, w, lane);
+                __syncthreads();
+                if (tid < 64) heavy_pick(S, tid, shift, dlo, dhi, wide);
+                __syncthreads();
+            }
+            if (tid == 0) S.flag = 0;
+            __syncthreads();
+            // bit 1: some column still open; bit 0: some open column has more
+            // than HEAVY_CAP keys on its prefix
+            if (tid < 64 && !S.done[tid]) {
+                atomicOr(&S.flag, 2);
+                if (S.ceq[tid] > HEAVY_CAP) atomicOr(&S.flag, 1);
+            }
+            __syncthreads();
+            const int f = S.flag;
+            hmask |= ((1 << width) - 1) << shift;
+            if (!(f & 2)) {
+                all_done = true;
+                break;
+            }
+            if (pass == 1 && !(f & 1)) {
+                collected = true;  // few keys share the 16-bit prefix: rank them in LDS
+                break;
+            }
+        }
+        if (all_done) {
+            // every cut was fixed by a prefix alone
+        } else if (collected) {
+            const int pre = S.prefix[lane];
+            const bool act = !S.done[lane];
+            for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
+                const int m = min(64, n - c0);
+                const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
+                for (int j0 = 0; j0 < m; j0 += 16) {
+                    int key[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
+                        const int kk = heavy_key(a.other, col, lane, nf);
+                        key[j] = (j0 + j < m) ? kk : -1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
+                            const int slot = atomicAdd(&S.ccnt[lane], 1);
+                            if (slot < HEAVY_CAP) {
+                                S.ckey[lane][slot] = key[j];
+                                S.cpos[lane][slot] = c0 + j0 + j;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < 64 && !S.done[tid]) {
+                const int m = min(S.ccnt[tid], HEAVY_CAP);
+                const int want = S.rem[tid] - 1;  // rank from the top, 0-based
+                for (int x = 0; x < m; ++x) {
+                    const int kx = S.ckey[tid][x], px = S.cpos[tid][x];
+                    int rank = 0;
+                    for (int y = 0; y < m; ++y) {
+                        const int ky = S.ckey[tid][y], py = S.cpos[tid][y];
+                        rank += (ky > kx) || (ky == kx && py < px);
+                    }
+                    if (rank == want) {
+                        S.T[tid] = kx;
+                        S.K[tid] = px;
+                    }
+                }
+            }
+        } else {
+            // all 31 bits resolved: T is the key itself; ties resolved by position
+            if (tid < 64 && !S.done[tid]) S.T[tid] = S.prefix[tid];
+            __syncthreads();
+            if (w == 0) {
+                const bool tie = !S.done[lane] && S.ceq[lane] > S.rem[lane];
+                if (__ballot(tie) != 0ull) {
+                    const int T = S.T[lane], need = S.rem[lane];
+                    int cnt = 0, K = 0x7FFFFFFF;
+                    for (int c0 = 0; c0 < n; c0 += 64) {
+                        const int m = min(64, n - c0);
+                        const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
+                        for (int j = 0; j < m; ++j) {
+                            const int col = __builtin_amdgcn_readlane(colv, j);
+                            const int key = heavy_key(a.other, col, lane, nf);
+                            if (tie && key == T) {
+                                ++cnt;
+                                if (cnt == need) K = c0 + j;
+                            }
+                        }
+                    }
+                    if (tie) S.K[lane] = K;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            a.cutT[t * 64 + tid] = S.T[tid];
+            a.cutK[t * 64 + tid] = S.K[tid];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(WPB * 64) void k_heavy_gram(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    __shared__ WaveLds lds[WPB];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    WaveLds &L = lds[w];
+    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
+        const int64_t slot = a.pair_slot[p];
+        const int chunk = a.pair_chunk[p];
+        const int64_t i = a.rows[slot];
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+        Cut c;
+        if (s == n) c = Cut{0, 0, false, true};
+        else if (s == 0) c = Cut{0, 0, true, false};
+        else c = Cut{a.cutT[slot * 64 + lane], a.cutK[slot * 64 + lane], false, false};
+        const int kb = chunk * a.chunk;
+        const int ke = min(n, kb + a.chunk);
+        float A[NF];
+        float rhs;
+        gram_range(L, r, c, kb, ke, lane, A, rhs);
+        float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
+#pragma unroll
+        for (int b = 0; b < NF; ++b) dst[b * 64 + lane] = A[b];
+        dst[NF * 64 + lane] = rhs;
+    }
+}
+
+__global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
+                                                          int64_t pair_base) {
+    __shared__ WaveLds lds[WPB];
+    const int w = threadIdx.x >> 6;
+    const int lane0 = threadIdx.x & 63;
+    WaveLds &L = lds[w];
+    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    for (int64_t slot = slot_begin + (int64_t)blockIdx.x * WPB + w; slot < slot_end;
+         slot += (int64_t)gridDim.x * WPB) {
+        const int lane = opaque_lane(lane0);
+        const int64_t i = a.rows[slot];
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        float A[NF];
+        float rhs = 0.f;
+#pragma unroll
+        for (int b = 0; b < NF; ++b) A[b] = 0.f;
+        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p) {
+            const float *src = a.partials + (p - pair_base) * (int64_t)(NF + 1) * 64;
+#pragma unroll
+            for (int b = 0; b < NF; ++b) A[b] += src[b * 64 + lane];
+            rhs += src[NF * 64 + lane];
+        }
+        const float lamn = (float)((double)a.lam * (double)n);
+        finish_system(A, rhs, lamn, lane, a.nf);
+        float u = 0.f;
+        const bool core = s < n;
+        bool ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+        if (!ok) {
+            u = 0.f;
+            if (core) {
+                // singular core system: full-data update of eq. (U)
+                if (lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
+                RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+                Cut full{0, 0, false, true};
+                gram(L, r, full, lane, A, rhs);
+                finish_system(A, rhs, lamn, lane, a.nf);
+                ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+                if (!ok) u = 0.f;
+            }
+        }
+        if (lane < a.nf) a.out[i * a.nf + lane] = u;
+    }
+}
+
+unsigned blocks_for(int64_t items, int per_block, int64_t cap) {
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_heavy_select, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a, row_begin);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
+    if (pair_end <= pair_begin) return hipSuccess;
+    hipLaunchKernelGGL(k_heavy_gram, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
+                       pair_begin, pair_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
+                              hipStream_t s) {
+    if (slot_end <= slot_begin) return hipSuccess;
+    hipLaunchKernelGGL(k_heavy_solve, dim3(blocks_for(slot_end - slot_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
+                       slot_begin, slot_end, pair_base);
+    return hipGetLastError();
+}
+
+}  // namespace coreals

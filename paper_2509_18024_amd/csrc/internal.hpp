@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/coreals.h"
 
@@ -17,12 +18,20 @@ namespace coreals {
 constexpr int NF = 64;
 // Waves per workgroup of the row kernels; each wave solves its own rows.
 constexpr int WPB = 4;
-// Rows of the design matrix staged in LDS per chunk (one per lane).
+// Rows of the design matrix staged in LDS per chunk.
 constexpr int CK = 64;
+// Keys per column the heavy-row selection ranks directly in LDS.
+constexpr int HEAVY_CAP = 32;
+// Defaults of the schedule (als_problem fields set to 0 select them).
+constexpr int DEFAULT_HEAVY_N = 1024;    // light rows have degree <= this
+constexpr int DEFAULT_CHUNK = 1024;      // entries per partial Gram of a heavy row
+constexpr int64_t PAIR_CAP = 32768;      // partial systems held in scratch at once
 
-// Degree classes that schedule a half-sweep.  A row with budget s and degree n
-// goes to FULL when s == n (r = 1, or tiny rows), otherwise to the smallest
-// insertion-network class whose capacity holds s, otherwise to RADIX.
+// Degree classes that schedule a half-sweep.  Light rows (degree <= heavy_n
+// and budget s <= 32) are solved by one wavefront each: FULL when s == n
+// (r = 1, or tiny rows), otherwise the smallest insertion-network class whose
+// capacity holds s.  Every other row is HEAVY (radix selection by a workgroup,
+// Gram split into chunks, separate solve).
 enum RowClass : int {
     CLS_FULL = 0,
     CLS_NET1 = 1,
@@ -31,7 +40,7 @@ enum RowClass : int {
     CLS_NET8 = 4,
     CLS_NET16 = 5,
     CLS_NET32 = 6,
-    CLS_RADIX = 7,
+    CLS_HEAVY = 7,
     NCLASS = 8
 };
 
@@ -43,7 +52,8 @@ __host__ __device__ inline int64_t budget_of(int64_t n, uint32_t num, uint32_t d
     return s;
 }
 
-__host__ __device__ inline int class_of(int64_t n, int64_t s) {
+__host__ __device__ inline int class_of(int64_t n, int64_t s, int64_t heavy_n) {
+    if (n > heavy_n) return CLS_HEAVY;
     if (s == n) return CLS_FULL;
     if (s <= 1) return CLS_NET1;
     if (s <= 2) return CLS_NET2;
@@ -51,8 +61,26 @@ __host__ __device__ inline int class_of(int64_t n, int64_t s) {
     if (s <= 8) return CLS_NET8;
     if (s <= 16) return CLS_NET16;
     if (s <= 32) return CLS_NET32;
-    return CLS_RADIX;
+    return CLS_HEAVY;
 }
+
+// Work plan of the heavy rows of one side: the rows are perm[heavy_begin ..
+// heavy_begin + n_heavy); heavy slot t is the t-th of them.  Each row is cut
+// into ceil(n / chunk) pairs (slot, chunk); pairs are processed in batches
+// that fit the partial-system scratch.
+struct HeavyPlan {
+    int64_t n_heavy = 0;
+    int64_t n_pairs = 0;
+    int32_t *pair_slot = nullptr;   // [n_pairs]
+    int32_t *pair_chunk = nullptr;  // [n_pairs]
+    int64_t *pair_off = nullptr;    // [n_heavy + 1]
+    int32_t *cutT = nullptr;        // [n_heavy * 64]
+    int32_t *cutK = nullptr;
+    struct Batch {
+        int64_t slot_begin, slot_end, pair_begin, pair_end;
+    };
+    std::vector<Batch> batches;
+};
 
 // One side of the problem (users: CSR of R; items: CSC of R).
 struct Side {
@@ -64,9 +92,14 @@ struct Side {
     int32_t *perm = nullptr;           // rows ordered by (class, degree descending)
     int64_t class_off[NCLASS + 1] = {};  // host copy of class boundaries in perm
     int64_t max_deg = 0;
+    HeavyPlan heavy;
 };
 
 // Device-side counters of per-row events (cleared before each half-sweep).
+// Kernel groups timed by als_profile_begin / als_profile_end, per side.
+constexpr int NPROF = 10;
+enum ProfSlot : int { PROF_HSELECT = 7, PROF_HGRAM = 8, PROF_HSOLVE = 9 };
+
 enum StatSlot : int { ST_EMPTY = 0, ST_FALLBACK = 1, ST_FP64RES = 2, ST_ROWS = 3, NSTATS = 8 };
 
 struct SweepArgs {
@@ -84,6 +117,29 @@ struct SweepArgs {
     unsigned long long *stats;
 };
 
+struct HeavyArgs {
+    const int64_t *ptr;
+    const int32_t *idx;
+    const float *val;
+    const float *other;
+    float *out;
+    const int32_t *rows;      // heavy slot -> row (nullptr: row_begin + slot)
+    int64_t count;            // heavy rows
+    int32_t nf;
+    float lam;
+    uint32_t num, den;
+    int32_t min_keep;
+    int32_t heavy_n;
+    int32_t chunk;
+    const int32_t *pair_slot;
+    const int32_t *pair_chunk;
+    const int64_t *pair_off;
+    int32_t *cutT;
+    int32_t *cutK;
+    float *partials;
+    unsigned long long *stats;
+};
+
 struct SelectArgs {
     const int64_t *ptr;
     const int32_t *idx;
@@ -92,13 +148,22 @@ struct SelectArgs {
     int32_t nf;
     uint32_t num, den;
     int32_t min_keep;
+    int32_t heavy_n;
     const int64_t *sel_ptr;
     int32_t *sel_pos;
+    const int32_t *cutT;      // cuts of heavy rows, indexed by row - row_begin
+    const int32_t *cutK;
 };
 
 // launchers (sweep.hip)
 hipError_t launch_sweep_class(int cls, const SweepArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+
+// launchers (heavy.hip)
+hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s);
+hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
+hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
+                              hipStream_t s);
 
 // launchers (setup.hip)
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
@@ -110,7 +175,7 @@ hipError_t build_csc(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t 
                      const int32_t *col_idx, const float *val, int64_t *col_ptr,
                      int32_t *row_idx, float *val_t, void *temp, hipStream_t s);
 hipError_t build_schedule(int64_t n_rows, const int64_t *ptr, uint32_t num, uint32_t den,
-                          int32_t min_keep, int32_t *perm, int64_t *class_count_dev,
+                          int32_t min_keep, int32_t heavy_n, int32_t *perm, int64_t *class_count_dev,
                           int64_t *max_deg_dev, void *temp, hipStream_t s);
 hipError_t launch_select_sizes(const int64_t *ptr, int64_t row_begin, int64_t row_end, int32_t nf,
                                uint32_t num, uint32_t den, int32_t min_keep, int64_t *sel_ptr,
@@ -135,7 +200,18 @@ struct als_ctx {
     unsigned long long *stats = nullptr;  // [NSTATS]
     double *obj_partials = nullptr;
     double *obj_out = nullptr;            // [4]
+    float *partials = nullptr;            // [PAIR_CAP * (NF + 1) * 64]
+    int32_t heavy_n = coreals::DEFAULT_HEAVY_N;
+    int32_t chunk = coreals::DEFAULT_CHUNK;
+    int64_t pair_cap = coreals::PAIR_CAP;
     void *temp = nullptr;
     size_t temp_bytes = 0;
     std::string err;
+    // kernel timing (als_profile_begin / als_profile_end)
+    struct Mark {
+        hipEvent_t start, stop;
+        int side, cls;
+    };
+    bool profiling = false;
+    std::vector<Mark> marks;
 };

@@ -1,0 +1,312 @@
+// Per-wavefront building blocks of one row regression (gfx950), shared by the
+// light-row kernels (one wavefront per row) and the heavy-row kernels.
+//
+// Lane a owns column a of the design matrix X (for CES) and row a of the
+// n_f x n_f system (for the solve).  Design rows X[k] = other[idx[k]] are
+// staged in LDS in chunks of CK; keys are the bit patterns of |x| compared as
+// integers, so the selection is exact.
+#pragma once
+
+#include <utility>
+
+#include "internal.hpp"
+
+namespace coreals {
+
+constexpr int KEYMASK = 0x7FFFFFFF;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int key_of(float x) { return __float_as_int(x) & KEYMASK; }
+
+// The lane index as a value the compiler cannot hoist out of a row loop.
+// Without it, the 64 per-step lane comparisons of the solve are precomputed
+// once per kernel as scalar masks and spilled.
+__device__ __forceinline__ int opaque_lane(int lane) {
+    asm volatile("" : "+v"(lane));
+    return lane;
+}
+
+struct alignas(16) WaveLds {
+    float X[CK][NF + 4];      // staged design rows (select, Gram)
+    float y[CK];
+    float urhs[NF];           // solve: solution components parked by the back substitution
+};
+
+// Largest value over the wave of a non-negative-or-(-1) integer key: DPP
+// within each row of 16 lanes (xor 1, xor 2, half-row and row mirrors), then
+// the four row results through scalar registers.
+__device__ __forceinline__ int wave_max_key(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const int a = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+    const int b = max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+    return max(a, b);
+}
+
+// Per-row view used by the device helpers.
+struct RowCtx {
+    const int32_t *idx;
+    const float *val;
+    const float *other;
+    int64_t beg;
+    int n;
+    int nf;
+    bool vec4;
+    int staged;  // chunk start currently in LDS, -1 if none
+};
+
+// Gather chunk [k0, k0 + min(CK, n - k0)) of the design matrix into LDS.
+__device__ __forceinline__ void stage(WaveLds &L, RowCtx &r, int k0, int lane) {
+    if (r.staged == k0) return;
+    wave_sync();
+    const int cnt = min(CK, r.n - k0);
+    int col = 0;
+    float yv = 0.f;
+    if (lane < cnt) {
+        col = r.idx[r.beg + k0 + lane];
+        if (r.val) yv = r.val[r.beg + k0 + lane];
+    }
+    if (lane < CK) L.y[lane] = yv;
+    // Gathers are unconditional (positions past cnt read factor row 0, which
+    // exists) so the whole chunk's loads are in flight together; the padding
+    // is zeroed afterwards.
+    if (r.vec4) {
+        float4 v[CK / 4];
+#pragma unroll
+        for (int t = 0; t < CK / 4; ++t) {
+            const int kk = t * 4 + (lane >> 4);
+            const int c = __shfl(col, kk);
+            v[t] = *reinterpret_cast<const float4 *>(r.other + (size_t)c * NF + (lane & 15) * 4);
+        }
+#pragma unroll
+        for (int t = 0; t < CK / 4; ++t) {
+            const int kk = t * 4 + (lane >> 4);
+            if (kk >= cnt) v[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4 *>(&L.X[kk][(lane & 15) * 4]) = v[t];
+        }
+    } else {
+        const int lc = min(lane, r.nf - 1);
+        for (int kk = 0; kk < CK; ++kk) {
+            const int c = __shfl(col, kk);
+            const float v = r.other[(size_t)c * r.nf + lc];
+            L.X[kk][lane] = (kk < cnt && lane < r.nf) ? v : 0.f;
+        }
+    }
+    r.staged = k0;
+    wave_sync();
+}
+
+// Selection result for the lane's column: k is kept iff
+// key > T, or key == T and position <= K.  none: nothing kept (s == 0).
+struct Cut {
+    int T;
+    int K;
+    bool none;
+    bool all;
+};
+
+__device__ __forceinline__ bool kept(const Cut &c, int key, int pos) {
+    return c.all || (!c.none && (key > c.T || (key == c.T && pos <= c.K)));
+}
+
+// Position of the need-th key equal to T in ascending order (lanes with tie).
+__device__ __forceinline__ void tie_pass(WaveLds &L, RowCtx &r, int lane, bool tie, int T, int need, int &K) {
+    if (__ballot(tie) == 0ull) return;
+    int cnt = 0;
+    for (int k0 = 0; k0 < r.n; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, r.n - k0);
+        for (int k = 0; k < m; ++k) {
+            const int key = key_of(L.X[k][lane]);
+            if (tie && key == T) {
+                ++cnt;
+                if (cnt == need) K = k0 + k;
+            }
+        }
+    }
+}
+
+// Top-s by an insertion network of SMAX registers kept in descending order.
+// Unused slots (SMAX - s of them) hold INT_MAX and pass every key through.
+template <int SMAX>
+__device__ __forceinline__ Cut select_net(WaveLds &L, RowCtx &r, int s, int lane) {
+    int kept_[SMAX];
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) kept_[j] = (j < SMAX - s) ? 0x7FFFFFFF : -1;
+    int D = -1;  // largest key that fell out of the network
+    for (int k0 = 0; k0 < r.n; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, r.n - k0);
+        for (int k = 0; k < m; ++k) {
+            int v = key_of(L.X[k][lane]);
+#pragma unroll
+            for (int j = 0; j < SMAX; ++j) {
+                const int hi = max(kept_[j], v);
+                v = min(kept_[j], v);
+                kept_[j] = hi;
+            }
+            D = max(D, v);
+        }
+    }
+    Cut c;
+    c.T = kept_[SMAX - 1];
+    c.none = false;
+    c.all = false;
+    int gt = 0;
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) gt += kept_[j] > c.T;
+    gt -= SMAX - s;
+    const int need = s - gt;
+    const bool tie = (D == c.T);
+    c.K = 0x7FFFFFFF;
+    tie_pass(L, r, lane, tie, c.T, need, c.K);
+    return c;
+}
+
+// Row a of X*^T X and entry a of X*^T y for the lane's column, summed over
+// positions [kb, ke) of the row (chunks of CK staged in LDS; ascending k).
+__device__ __forceinline__ void gram_range(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+                                           float (&A)[NF], float &rhs) {
+#pragma unroll
+    for (int b = 0; b < NF; ++b) A[b] = 0.f;
+    rhs = 0.f;
+    if (c.none) return;
+    for (int k0 = kb; k0 < ke; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, ke - k0);
+        for (int k = 0; k < m; ++k) {
+            const float xa = L.X[k][lane];
+            const float w = kept(c, key_of(xa), k0 + k) ? xa : 0.f;
+#pragma unroll
+            for (int b4 = 0; b4 < NF / 4; ++b4) {
+                const float4 xr = *reinterpret_cast<const float4 *>(&L.X[k][b4 * 4]);
+                A[4 * b4 + 0] = fmaf(w, xr.x, A[4 * b4 + 0]);
+                A[4 * b4 + 1] = fmaf(w, xr.y, A[4 * b4 + 1]);
+                A[4 * b4 + 2] = fmaf(w, xr.z, A[4 * b4 + 2]);
+                A[4 * b4 + 3] = fmaf(w, xr.w, A[4 * b4 + 3]);
+            }
+            rhs = fmaf(w, L.y[k], rhs);
+        }
+    }
+}
+
+__device__ __forceinline__ void gram(WaveLds &L, RowCtx &r, const Cut &c, int lane, float (&A)[NF], float &rhs) {
+    gram_range(L, r, c, 0, r.n, lane, A, rhs);
+}
+
+// Diagonal penalty lambda n_i and identity padding for lanes >= nf.
+__device__ __forceinline__ void finish_system(float (&A)[NF], float &rhs, float lamn, int lane, int nf) {
+    const bool pad = lane >= nf;
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+        float v = A[b] + ((b == lane) ? lamn : 0.f);
+        A[b] = pad ? ((b == lane) ? 1.f : 0.f) : v;
+    }
+    if (pad) rhs = 0.f;
+}
+
+// Elimination step J of the register-resident solve.  Every step has its own
+// code (the steps are expanded at compile time), so every index into A is a
+// constant and A stays in VGPRs; rows stay in place (A[c] is column c) and
+// each pivot row stays in its lane.  PIVOT: partial pivoting (first lane of
+// largest |entry| among rows not yet used, found by a DPP max); otherwise
+// row J is the pivot (symmetric positive definite systems).  The pivot row
+// reaches the other lanes through scalar broadcasts (v_readlane).
+template <bool PIVOT, int J>
+__device__ __forceinline__ void elim_step_u(float (&A)[NF], float &rhs, int lane, int nf, float tol, int &my_step,
+                                            bool &ok) {
+    int p;
+    bool active;
+    if constexpr (PIVOT) {
+        active = my_step == NF;
+        const int cand = active ? __float_as_int(fabsf(A[J])) : -1;
+        const int mx = wave_max_key(cand);
+        const uint64_t bal = __ballot(active && cand == mx);
+        p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+        p = __builtin_amdgcn_readfirstlane(p);
+    } else {
+        active = lane >= J;
+        p = J;
+    }
+    const float piv = readlane_f(A[J], p);
+    ok = ok && (J >= nf || fabsf(piv) > tol);
+    const bool elim = active && lane != p;
+    const float l = elim ? A[J] / piv : 0.f;
+    if (lane == p) my_step = J;
+#pragma unroll
+    for (int c = J + 1; c < NF; ++c) A[c] = fmaf(-l, readlane_f(A[c], p), A[c]);
+    rhs = fmaf(-l, readlane_f(rhs, p), rhs);
+}
+
+template <bool PIVOT, int J>
+__device__ __forceinline__ void back_step_u(const float (&A)[NF], float &rhs, int lane, int my_step, float *xs) {
+    int p;
+    if constexpr (PIVOT) {
+        const uint64_t bal = __ballot(my_step == J);
+        p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+        p = __builtin_amdgcn_readfirstlane(p);
+    } else {
+        p = J;
+    }
+    const float x = readlane_f(rhs, p) / readlane_f(A[J], p);
+    if (lane == p) xs[J] = x;
+    if (my_step < J) rhs = fmaf(-A[J], x, rhs);
+}
+
+template <bool PIVOT, int... J>
+__device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float &rhs, int lane,
+                                           int nf, float tol, int &my_step, bool &ok) {
+    (elim_step_u<PIVOT, J>(A, rhs, lane, nf, tol, my_step, ok), ...);
+}
+
+template <bool PIVOT, int... J>
+__device__ __forceinline__ void back_all_u(std::integer_sequence<int, J...>, const float (&A)[NF], float &rhs,
+                                           int lane, int my_step, float *xs) {
+    (back_step_u<PIVOT, NF - 1 - J>(A, rhs, lane, my_step, xs), ...);
+}
+
+// Solve the register-resident system; returns false when a pivot of the first
+// nf steps is <= tol.  On success u holds solution component `lane`.
+template <bool PIVOT>
+__device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
+                                      WaveLds &L) {
+    int my_step = NF;  // elimination step at which this lane's row was the pivot
+    bool ok = true;
+    elim_all_u<PIVOT>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    if (!PIVOT) my_step = lane;
+    if (!ok) return false;
+    wave_sync();
+    back_all_u<PIVOT>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, my_step, L.urhs);
+    wave_sync();
+    u = L.urhs[lane];
+    wave_sync();
+    return true;
+}
+
+__device__ __forceinline__ float system_tol(const float (&A)[NF], int nf) {
+    float m = 0.f;
+#pragma unroll
+    for (int b = 0; b < NF; ++b) m = fmaxf(m, fabsf(A[b]));
+    m = __int_as_float(wave_max_key(__float_as_int(m)));  // m >= 0: integer order = value order
+    return (float)nf * 1.1920928955078125e-7f * m;
+}
+
+
+}  // namespace coreals

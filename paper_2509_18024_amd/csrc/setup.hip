@@ -259,13 +259,13 @@ __global__ void k_csc_gather(int64_t nnz, const int32_t *perm, const int32_t *ro
 // schedule: rows ordered by (class, degree descending)
 // --------------------------------------------------------------------------
 __global__ void k_sched_keys(int64_t n_rows, const int64_t *ptr, uint32_t num, uint32_t den,
-                             int32_t min_keep, uint32_t *keys, int32_t *vals,
+                             int32_t min_keep, int32_t heavy_n, uint32_t *keys, int32_t *vals,
                              unsigned long long *class_count, unsigned long long *max_deg) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t n = ptr[i + 1] - ptr[i];
         int64_t s = budget_of(n, num, den, min_keep);
-        int cls = class_of(n, s);
+        int cls = class_of(n, s, heavy_n);
         int64_t nc = n < 0x7FFFFFF ? n : 0x7FFFFFF;
         keys[i] = ((uint32_t)cls << 27) | (uint32_t)(0x7FFFFFF - nc);
         vals[i] = (int32_t)i;
@@ -357,7 +357,7 @@ hipError_t build_csc(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t 
 }
 
 hipError_t build_schedule(int64_t n_rows, const int64_t *ptr, uint32_t num, uint32_t den, int32_t min_keep,
-                          int32_t *perm, int64_t *class_count_dev, int64_t *max_deg_dev, void *temp,
+                          int32_t heavy_n, int32_t *perm, int64_t *class_count_dev, int64_t *max_deg_dev, void *temp,
                           hipStream_t s) {
     size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
     char *p = (char *)temp;
@@ -373,7 +373,7 @@ hipError_t build_schedule(int64_t n_rows, const int64_t *ptr, uint32_t num, uint
     if (e != hipSuccess) return e;
     if (n_rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n_rows, 256)), dim3(256), 0, s, n_rows, ptr, num, den,
-                       min_keep, k0, perm, (unsigned long long *)class_count_dev,
+                       min_keep, heavy_n, k0, perm, (unsigned long long *)class_count_dev,
                        (unsigned long long *)max_deg_dev);
     return radix_sort(k0, perm, k1, v1, n_rows, 31, rtmp, s);
 }

@@ -177,8 +177,43 @@ def test_c1_plain_als_ten_iterations(ora):
 
 
 @gpu
+def test_c2_core_teacher_forced_every_iteration(ora):
+    """C2 recipe at 5% scale, r = 1/10, 15 iterations on the GPU.  At every
+    half-sweep the oracle recomputes the same half-sweep from the GPU's own
+    input factors; the two must agree within 1e-4 (relative Frobenius)."""
+    import torch
+    p = synth.c2_core(scale=0.05)
+    note(f"[C2 small, teacher forced] n_u={p.n_u} n_m={p.n_m} nnz={p.nnz}")
+    als = make_als(p)
+    cp, ri, vt = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+    M = torch.from_numpy(p.M0).cuda()
+    U = torch.empty(p.n_u, p.n_f, dtype=torch.float32, device="cuda")
+    worst = 0.0
+    for t in range(p.iters):
+        Min = M.cpu().numpy().astype(np.float64)
+        als.half_sweep_users(M, U)
+        Uo, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, Min, p.lam, 1, 10, 1)
+        eu = rel_fro(U.cpu().numpy(), Uo)
+        Uin = U.cpu().numpy().astype(np.float64)
+        als.half_sweep_items(U, M)
+        Mo, _ = ora.half_sweep(cp, ri, vt, Uin, p.lam, 1, 10, 1)
+        em = rel_fro(M.cpu().numpy(), Mo)
+        worst = max(worst, eu, em)
+        assert eu <= 1e-4 and em <= 1e-4, (t, eu, em)
+    note(f"  worst per-half-sweep rel err over {p.iters} iterations: {worst:.2e}")
+    als.close()
+
+
+@gpu
 def test_c2_core_rmse_gap_small_scale(ora):
-    """C2 recipe at 5% scale, r = 1/10, 15 iterations: RMSE gap <= 1e-3."""
+    """C2 recipe at 5% scale, r = 1/10, 15 iterations: end-to-end RMSE of the
+    FP32 GPU run against the FP64 oracle run from the same M0.
+
+    Both runs follow Algorithm 2, but CES is a discontinuous rule: when two
+    magnitudes of a column differ by less than the FP32 rounding of the
+    factors (~1e-6 relative), the two runs keep different entries and their
+    trajectories separate.  Each half-sweep is checked at 1e-4 by the
+    teacher-forced test above; the end-to-end gap is bounded at 2e-3 here."""
     import torch
     from paper_2509_18024_amd.als import run_als
     p = synth.c2_core(scale=0.05)
@@ -190,7 +225,7 @@ def test_c2_core_rmse_gap_small_scale(ora):
     ro = ora.objective(p.row_ptr, p.col_idx, p.val, Uo, Mo, p.lam)[2]
     rg = hist[-1]["rmse"]
     note(f"  rmse gpu {rg:.6f} oracle {ro:.6f} gap {abs(rg - ro):.2e}")
-    assert abs(rg - ro) <= 1e-3
+    assert abs(rg - ro) <= 2e-3
     als.close()
 
 
@@ -272,4 +307,83 @@ def test_deterministic_repeat():
     U2 = als.half_sweep_users(M).clone()
     torch.cuda.synchronize()
     assert torch.equal(U1, U2)
+    als.close()
+
+
+def heavy_cases():
+    """Schedules that push many rows through the heavy-row kernels: small light
+    limit, short chunks (several partial systems per row) and a tiny partial
+    scratch (many batches)."""
+    p1 = synth.random_problem(12, 120, 700, 64, 0.3, budget=(1, 4), heavy_rows=(0, 5, 9))
+    p2 = synth.random_problem(13, 400, 90, 16, 0.35, budget=(1, 1), heavy_rows=(1,))
+    p3 = synth.random_problem(14, 600, 200, 64, 0.25, budget=(1, 10), min_keep=0, heavy_rows=(2, 3))
+    return [("heavy_r1/4", p1), ("heavy_full_nf16", p2), ("heavy_r1/10_minkeep0", p3)]
+
+
+HEAVY_KW = dict(heavy_min_degree=64, heavy_chunk=32, heavy_pair_cap=64)
+
+
+@gpu
+@pytest.mark.parametrize("which", range(3))
+def test_heavy_rows_match_oracle(ora, which):
+    import torch
+    name, p = heavy_cases()[which]
+    note(f"[heavy] {name} n_u={p.n_u} n_m={p.n_m} n_f={p.n_f} r={p.budget_num}/{p.budget_den}")
+    als = make_als(p, **HEAVY_KW)
+    from paper_2509_18024_amd import capi
+    counts = capi.als_class_counts(als.ctx)
+    note(f"  classes users {counts[0]} items {counts[1]}")
+    assert counts[0][7] + counts[1][7] > 0
+    M = torch.from_numpy(p.M0).cuda()
+    U = als.half_sweep_users(M)
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), p.lam,
+                           p.budget_num, p.budget_den, p.min_keep)
+    eu = rel_fro(U.cpu().numpy(), Uo)
+    U32 = Uo.astype(np.float32)
+    Mg = als.half_sweep_items(torch.from_numpy(U32).cuda())
+    torch.cuda.synchronize()
+    cp, ri, vt = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+    Mo, _ = ora.half_sweep(cp, ri, vt, U32.astype(np.float64), p.lam, p.budget_num, p.budget_den,
+                           p.min_keep)
+    em = rel_fro(Mg.cpu().numpy(), Mo)
+    note(f"  users rel err {eu:.3e} items rel err {em:.3e}")
+    assert eu <= 1e-4 and em <= 1e-4
+    for side, other, rp_, ci_, n_rows in ((0, p.M0, p.row_ptr, p.col_idx, p.n_u),
+                                          (1, U32, cp, ri, p.n_m)):
+        sel_ptr, sel = als.core_select(side, torch.from_numpy(np.ascontiguousarray(other)).cuda(), 0,
+                                       n_rows)
+        torch.cuda.synchronize()
+        rp, rs = ora.core_select_rows(np.arange(n_rows), rp_, ci_, other.astype(np.float64),
+                                      p.budget_num, p.budget_den, p.min_keep)
+        assert np.array_equal(sel_ptr.cpu().numpy(), rp)
+        assert np.array_equal(sel.cpu().numpy(), rs)
+    als.close()
+
+
+@gpu
+def test_wide_row_selection_and_sweep(ora):
+    """A user with 70000 ratings: the heavy selection's 32-bit counting path."""
+    import torch
+    rng = np.random.default_rng(15)
+    n_u, n_m, nf = 6, 70000, 8
+    rows = [np.arange(n_m)] + [np.sort(rng.choice(n_m, 300, replace=False)) for _ in range(n_u - 1)]
+    rp = np.zeros(n_u + 1, np.int64)
+    np.cumsum([len(r) for r in rows], out=rp[1:])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(len(ci)).astype(np.float32)
+    M0 = rng.standard_normal((n_m, nf)).astype(np.float32)
+    M0[rng.random(M0.shape) < 0.01] = 0.0  # ties at zero
+    p = synth.Problem("wide", n_u, n_m, nf, rp, ci, val, 0.05, 1, 10, 1, 1, M0)
+    note("[wide row] n=70000")
+    als = make_als(p)
+    sel_ptr, sel = als.core_select(0, torch.from_numpy(M0).cuda(), 0, n_u)
+    torch.cuda.synchronize()
+    rpo, rso = ora.core_select_rows(np.arange(n_u), rp, ci, M0.astype(np.float64), 1, 10, 1)
+    assert np.array_equal(sel_ptr.cpu().numpy(), rpo)
+    assert np.array_equal(sel.cpu().numpy(), rso)
+    U = als.half_sweep_users(torch.from_numpy(M0).cuda())
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(rp, ci, val, M0.astype(np.float64), 0.05, 1, 10, 1)
+    assert rel_fro(U.cpu().numpy(), Uo) <= 1e-4
     als.close()
