@@ -59,7 +59,7 @@ def class_work(deg, num, den, min_keep, nf, heavy_n=1024):
     s = budgets_of(deg, num, den, min_keep)
     cls = classes_of(deg, s, heavy_n)
     out = []
-    for c in range(10):
+    for c in range(12):
         m = cls == (c if c < 7 else 7)
         rows = int(m.sum())
         nnz = int(deg[m].sum())
@@ -75,16 +75,18 @@ def class_work(deg, num, den, min_keep, nf, heavy_n=1024):
             by, fl = (entry_bytes if ss > 0 else 0), 0.0
         elif c == 8:
             by, fl = entry_bytes, gram + rhs
+        elif c == 10:  # refinement residual: x_k . u per entry and the kept column sums
+            by, fl = entry_bytes, float(2 * nf * nnz + 2 * (ss + deg[m][full].sum()))
         else:
             by, fl = rows * (8 + 4 * nf), lu
         out.append({"rows": rows, "nnz": nnz, "bytes": by, "flops": fl})
     return out
 
 
-def time_variant(torch, CoreALS, run_als, prob, dev, budget, steps, warmup, tag):
+def time_variant(torch, CoreALS, run_als, prob, dev, budget, steps, warmup, tag, precision=0):
     from paper_2509_18024_amd import capi
     t0 = time.time()
-    als = CoreALS.from_problem(prob, dev, budget=budget)
+    als = CoreALS.from_problem(prob, dev, budget=budget, precision=precision)
     torch.cuda.synchronize()
     init_s = time.time() - t0
     counts = capi.als_class_counts(als.ctx)
@@ -113,6 +115,7 @@ def time_variant(torch, CoreALS, run_als, prob, dev, budget, steps, warmup, tag)
     ms = ms_total / steps
     res = {
         "budget": f"{budget[0]}/{budget[1]}",
+        "precision": ["fp32", "bf16+ir(fp32 residual)", "bf16+ir(fp64 residual)", "auto"][precision],
         "sweep_ms": ms,
         "sweep_s": ms / 1000.0,
         "solves_per_s": (prob.n_u + prob.n_m) / (ms / 1000.0),
@@ -229,22 +232,27 @@ def main():
     prob = synth.c3_batched(scale=args.scale)
     log(f"generated n_u={prob.n_u} n_m={prob.n_m} nnz={prob.nnz} in {time.time() - t:.1f}s")
 
-    variants = [("core_r1/10", (1, 10))]
+    # headline: core-elements ALS, r = 1/10, BF16 Gram + refinement (heavy rows);
+    # comparator: plain full-data ALS in FP32 on the same GPU
+    HEAD = "core_r1/10_bf16ir"
+    variants = [(HEAD, (1, 10), 1)]
     if not args.headline_only:
-        variants += [("core_r1/20", (1, 20)), ("core_r1/4", (1, 4)), ("full_als", (1, 1))]
+        variants += [("core_r1/10_fp32", (1, 10), 0), ("core_r1/20_bf16ir", (1, 20), 1),
+                     ("core_r1/4_bf16ir", (1, 4), 1), ("full_fp32", (1, 1), 0),
+                     ("full_bf16ir", (1, 1), 1)]
     results = {}
     head_als = None
-    for tag, b in variants:
-        als, res = time_variant(torch, CoreALS, run_als, prob, dev, b, args.steps, args.warmup, tag)
+    for tag, b, prec in variants:
+        als, res = time_variant(torch, CoreALS, run_als, prob, dev, b, args.steps, args.warmup, tag, prec)
         results[tag] = res
-        if tag == "core_r1/10":
+        if tag == HEAD:
             head_als = als
         else:
             als.close()
             del als
             torch.cuda.empty_cache()
 
-    head = results["core_r1/10"]
+    head = results[HEAD]
     # roofline of the dominant kernel (largest summed time in the timed region)
     deg_u = np.diff(prob.row_ptr)
     deg_i = np.bincount(prob.col_idx, minlength=prob.n_m)
@@ -294,7 +302,7 @@ def main():
         cpu = cpu_baseline(prob, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.3e} solves/s on {cpu['cores']} threads")
 
-    full = results.get("full_als")
+    full = results.get("full_fp32")
     line = {
         "metric": METRIC,
         "value": head["solves_per_s"],
@@ -306,19 +314,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32",
         "data": "synthetic",
         "config": {
             "workload": (f"c3_batched: n_u={prob.n_u}, n_m={prob.n_m}, n_f={prob.n_f}, "
                          f"nnz={prob.nnz}, user degree 1+Lomax(1.5) capped 50k, item popularity "
                          f"Zipf(1.1) water-filled at 50k, lambda={prob.lam}, core-elements r=1/10, "
-                         f"FP32; step = users + items half-sweep"),
+                         f"BF16 MFMA Gram + one refinement step on heavy rows, FP32 elsewhere; "
+                         f"step = users + items half-sweep"),
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep_s": head["sweep_s"],
-        "core_vs_full": {k: {kk: v[kk] for kk in ("budget", "sweep_s", "solves_per_s", "rmse",
+        "core_vs_full": {k: {kk: v[kk] for kk in ("budget", "precision", "sweep_s", "solves_per_s", "rmse",
                                                    "iterations_done")}
                          for k, v in results.items()},
         "method_rmse_gap_vs_full": ({k: v["rmse"] - full["rmse"] for k, v in results.items()}

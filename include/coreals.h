@@ -51,9 +51,12 @@ typedef enum {
 
 typedef enum {
     ALS_PREC_FP32 = 0,            /* FP32 Gram, FP32 solve                    */
-    ALS_PREC_BF16_IR = 1,         /* BF16 MFMA Gram (FP32 accumulate), FP32 LU,
-                                     one refinement step with an FP32 residual */
-    ALS_PREC_BF16_IR_FP64RES = 2  /* as above, refinement residual in FP64    */
+    ALS_PREC_BF16_IR = 1,         /* heavy rows: BF16 MFMA Gram (FP32 accumulate),
+                                     FP32 LU, one refinement step with an FP32
+                                     residual; light rows: FP32 Gram          */
+    ALS_PREC_BF16_IR_FP64RES = 2, /* as above, refinement residual in FP64    */
+    ALS_PREC_AUTO = 3             /* BF16 + refinement, FP64 residual when
+                                     lambda < 1e-3, FP32 residual otherwise   */
 } als_precision;
 
 #define ALS_VALIDATE 1u /* check ratings for NaN/Inf in als_init */
@@ -143,12 +146,12 @@ als_status objective(als_ctx *c, const float *U, const float *M, als_objective *
 /* Kernel timing for measurement.  After als_profile_begin, every half-sweep
  * records a pair of HIP events around each kernel (group) it launches (on the
  * problem's stream; no synchronisation is added).  als_profile_end syncs and
- * fills (host) ms[side*10 + k] with the summed time and launches[side*10 + k]
+ * fills (host) ms[side*12 + k] with the summed time and launches[side*12 + k]
  * with the number of launches since als_profile_begin.  side 0 = users,
  * 1 = items; k = 0: light full-data rows, 1..6: light rows with insertion
  * networks of capacity 1, 2, 4, 8, 16, 32, 7: heavy-row selection, 8: heavy-row
- * Gram chunks, 9: heavy-row solves.  Either array may be NULL.  Profiling then
- * stops. */
+ * Gram chunks, 9: heavy-row solves, 10: refinement residuals, 11: refinement
+ * solves.  Either array may be NULL.  Profiling then stops. */
 als_status als_profile_begin(als_ctx *c);
 als_status als_profile_end(als_ctx *c, double *ms, int64_t *launches);
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcoreals.so")
 
 ALS_OK, ALS_E_ARG, ALS_E_INDEX, ALS_E_VALUE, ALS_E_NOMEM, ALS_E_DEVICE, ALS_E_STATE = range(7)
-ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES = 0, 1, 2
+ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES, ALS_PREC_AUTO = 0, 1, 2, 3
 ALS_VALIDATE = 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
@@ -59,9 +59,9 @@ EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_ite
            "als_class_counts", "als_destroy", "als_last_error"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
-NPROF = 10
+NPROF = 12
 PROF_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy_select", "heavy_gram",
-              "heavy_solve"]
+              "heavy_solve", "heavy_resid", "heavy_refine"]
 
 
 def load():

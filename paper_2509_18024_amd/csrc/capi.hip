@@ -43,6 +43,7 @@ struct Layout {
     double *obj_partials;
     double *obj_out;
     float *partials;
+    double *resid;
     struct SideArrays {
         int32_t *pair_slot, *pair_chunk, *cutT, *cutK;
         int64_t *pair_off;
@@ -91,6 +92,7 @@ Layout carve(const als_problem &p, void *base) {
     L.obj_partials = c.take<double>((size_t)5 * objective_blocks());
     L.obj_out = c.take<double>(4);
     L.partials = c.take<float>((size_t)pair_cap_of(p) * (NF + 1) * 64);
+    L.resid = c.take<double>((size_t)pair_cap_of(p) * 64);
     for (int sd = 0; sd < 2; ++sd) {
         const int64_t nr = sd == 0 ? p.n_u : p.n_m;
         const int64_t hb = heavy_bound(p, nr), pb = pair_bound(p, nr);
@@ -195,6 +197,9 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         h.cutT = H.cutT;
         h.cutK = H.cutK;
         h.partials = c->partials;
+        h.resid = c->resid;
+        h.refine = 0;
+        h.fp64res = c->fp64res ? 1 : 0;
         h.stats = c->stats;
         if (c->p.budget_num < c->p.budget_den) {
             als_ctx::Mark mk{};
@@ -205,11 +210,24 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         for (const auto &b : H.batches) {
             als_ctx::Mark mg{}, ms{};
             HIP_CHECK(c, mark_begin(PROF_HGRAM, mg));
-            HIP_CHECK(c, launch_heavy_gram(h, b.pair_begin, b.pair_end, c->stream));
+            if (c->bf16) HIP_CHECK(c, launch_heavy_gram_bf16(h, b.pair_begin, b.pair_end, c->stream));
+            else HIP_CHECK(c, launch_heavy_gram(h, b.pair_begin, b.pair_end, c->stream));
             HIP_CHECK(c, mark_end(mg));
             HIP_CHECK(c, mark_begin(PROF_HSOLVE, ms));
+            h.refine = 0;
             HIP_CHECK(c, launch_heavy_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
             HIP_CHECK(c, mark_end(ms));
+            if (c->bf16) {
+                // one refinement step: chunk residuals, then the correction solve
+                als_ctx::Mark mr{}, m2{};
+                HIP_CHECK(c, mark_begin(PROF_HRESID, mr));
+                HIP_CHECK(c, launch_heavy_resid(h, b.pair_begin, b.pair_end, c->stream));
+                HIP_CHECK(c, mark_end(mr));
+                HIP_CHECK(c, mark_begin(PROF_HREFINE, m2));
+                h.refine = 1;
+                HIP_CHECK(c, launch_heavy_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                HIP_CHECK(c, mark_end(m2));
+            }
         }
     }
     if (st) {
@@ -241,8 +259,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (p->budget_den == 0 || p->budget_num == 0 || p->budget_num > p->budget_den)
         return fail(nullptr, ALS_E_ARG, "budget rate must satisfy 0 < num <= den%s");
     if (p->min_keep < 0) return fail(nullptr, ALS_E_ARG, "min_keep must be >= 0%s");
-    if (p->precision != ALS_PREC_FP32)
-        return fail(nullptr, ALS_E_ARG, "precision not supported by this build%s");
+    if (p->precision < ALS_PREC_FP32 || p->precision > ALS_PREC_AUTO)
+        return fail(nullptr, ALS_E_ARG, "unknown precision mode%s");
     if (!p->row_ptr || (p->nnz > 0 && (!p->col_idx || !p->val)))
         return fail(nullptr, ALS_E_ARG, "NULL CSR pointer%s");
     Layout probe = carve(*p, nullptr);
@@ -261,6 +279,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->obj_partials = L.obj_partials;
     c->obj_out = L.obj_out;
     c->partials = L.partials;
+    c->resid = L.resid;
+    c->bf16 = p->precision != ALS_PREC_FP32;
+    c->fp64res = p->precision == ALS_PREC_BF16_IR_FP64RES || (p->precision == ALS_PREC_AUTO && p->lambda < 1e-3);
     c->heavy_n = heavy_n_of(*p);
     c->chunk = chunk_of(*p);
     c->pair_cap = pair_cap_of(*p);

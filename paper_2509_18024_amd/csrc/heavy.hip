@@ -17,7 +17,16 @@
 //                   lane a writes row a of the system with coalesced stores).
 //   k_heavy_solve   one wavefront per row sums its partial systems in chunk
 //                   order (deterministic), adds lambda n_i, and solves it
-//                   (pivoted LU; LDL^T when s == n).
+//                   (pivoted LU).
+//
+// BF16 precision modes replace k_heavy_gram by k_heavy_gram_bf16 (the same
+// partial systems from bf16 MFMA tiles with FP32 accumulation) and add one
+// step of iterative refinement: k_heavy_resid forms the partial residuals
+// X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
+// second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the same
+// (re-factored) matrix and returns u + d.
+#include <type_traits>
+
 #include "rowops.hpp"
 
 namespace coreals {
@@ -325,6 +334,21 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         finish_system(A, rhs, lamn, lane, a.nf);
         float u = 0.f;
         const bool core = s < n;
+        if (a.refine) {
+            // second solve: rho = sum of chunk residuals - lambda n u, then u + A^-1 rho
+            const float u0 = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
+            double rho = 0.0;
+            for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p)
+                rho += a.resid[(p - pair_base) * 64 + lane];
+            rho -= (double)a.lam * (double)n * (double)u0;
+            if (lane >= a.nf) rho = 0.0;
+            float d = 0.f;
+            const bool ok = solve<true>(A, (float)rho, lane, a.nf, system_tol(A, a.nf), d, L);
+            if (!ok) continue;  // the first solve already used the full-data fallback
+            if (a.fp64res && lane == 0) atomicAdd(&a.stats[ST_FP64RES], 1ull);
+            if (lane < a.nf) a.out[i * a.nf + lane] = u0 + d;
+            continue;
+        }
         bool ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         if (!ok) {
             u = 0.f;
@@ -343,6 +367,149 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
     }
 }
 
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+// Partial system of one (row, chunk) pair from bf16 MFMA tiles.  The 64x64
+// block X*^T X is four 32x32 tiles (a-half, b-half); each 16-position slab of
+// the staged rows feeds v_mfma_f32_32x32x16_bf16 with A = W^T (W = kept
+// entries of X, lane m of half h holds column 32t+m, positions 8h..8h+7) and
+// B = X (same positions, column 32t+m).  Output lane l holds column l%32 of a
+// tile and rows 8(r/4) + 4(l/32) + r%4 in accumulator r.
+__global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    __shared__ WaveLds lds[WPB];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 31, h = lane >> 5;
+    WaveLds &L = lds[w];
+    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
+        const int64_t slot = a.pair_slot[p];
+        const int chunk = a.pair_chunk[p];
+        const int64_t i = a.rows[slot];
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+        Cut c[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = 32 * t + m;
+            if (s == n) c[t] = Cut{0, 0, false, true};
+            else if (s == 0) c[t] = Cut{0, 0, true, false};
+            else c[t] = Cut{a.cutT[slot * 64 + col], a.cutK[slot * 64 + col], false, false};
+        }
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[ta][tb][q] = 0.f;
+        float racc[2] = {0.f, 0.f};
+        const int kb = chunk * a.chunk;
+        const int ke = min(n, kb + a.chunk);
+        for (int k0 = kb; k0 < ke; k0 += CK) {
+            stage(L, r, k0, lane);
+            const int mrows = min(CK, ke - k0);
+            for (int s16 = 0; s16 < mrows; s16 += 16) {
+                bf16x8 av[2], bv[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int col = 32 * t + m;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int kk = s16 + 8 * h + e;
+                        const float x = kk < mrows ? L.X[kk][col] : 0.f;
+                        const float wv = kept(c[t], key_of(x), k0 + kk) ? x : 0.f;
+                        av[t][e] = (__bf16)wv;
+                        bv[t][e] = (__bf16)x;
+                        racc[t] = fmaf(wv, L.y[kk], racc[t]);
+                    }
+                }
+#pragma unroll
+                for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < 2; ++tb)
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ta], bv[tb], acc[ta][tb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) racc[t] += __shfl_xor(racc[t], 32);
+        float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = 8 * (q >> 2) + 4 * h + (q & 3);
+                    dst[(32 * tb + m) * 64 + 32 * ta + row] = acc[ta][tb][q];
+                }
+        if (h == 0) {
+            dst[NF * 64 + m] = racc[0];
+            dst[NF * 64 + 32 + m] = racc[1];
+        }
+    }
+}
+
+// Partial refinement residual of one (row, chunk) pair: rho_a = sum over kept
+// k of x_ka (y_k - x_k . u), with u the row's current solution (in `out`).
+// Lane k forms y_k - x_k . u for the staged rows, lane a then accumulates its
+// column.  FP64 accumulates in double throughout.
+template <bool FP64>
+__global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    using acc_t = typename std::conditional<FP64, double, float>::type;
+    __shared__ WaveLds lds[WPB];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    WaveLds &L = lds[w];
+    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
+        const int64_t slot = a.pair_slot[p];
+        const int chunk = a.pair_chunk[p];
+        const int64_t i = a.rows[slot];
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+        Cut c;
+        if (s == n) c = Cut{0, 0, false, true};
+        else if (s == 0) c = Cut{0, 0, true, false};
+        else c = Cut{a.cutT[slot * 64 + lane], a.cutK[slot * 64 + lane], false, false};
+        wave_sync();
+        L.urhs[lane] = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
+        acc_t acc = 0;
+        const int kb = chunk * a.chunk;
+        const int ke = min(n, kb + a.chunk);
+        for (int k0 = kb; k0 < ke; k0 += CK) {
+            stage(L, r, k0, lane);
+            const int mrows = min(CK, ke - k0);
+            acc_t rk = 0;
+            if (lane < mrows) {
+                acc_t dot = 0;
+#pragma unroll
+                for (int b4 = 0; b4 < NF / 4; ++b4) {
+                    const float4 xr = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
+                    dot += (acc_t)xr.x * (acc_t)L.urhs[4 * b4 + 0];
+                    dot += (acc_t)xr.y * (acc_t)L.urhs[4 * b4 + 1];
+                    dot += (acc_t)xr.z * (acc_t)L.urhs[4 * b4 + 2];
+                    dot += (acc_t)xr.w * (acc_t)L.urhs[4 * b4 + 3];
+                }
+                rk = (acc_t)L.y[lane] - dot;
+            }
+            L.rres[lane] = (double)rk;
+            wave_sync();
+            for (int kk = 0; kk < mrows; ++kk) {
+                const float x = L.X[kk][lane];
+                if (kept(c, key_of(x), k0 + kk)) acc += (acc_t)x * (acc_t)L.rres[kk];
+            }
+            wave_sync();
+        }
+        a.resid[(p - pair_begin) * 64 + lane] = (double)acc;
+    }
+}
+
 unsigned blocks_for(int64_t items, int per_block, int64_t cap) {
     int64_t b = (items + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -351,6 +518,24 @@ unsigned blocks_for(int64_t items, int per_block, int64_t cap) {
 }
 
 }  // namespace
+
+hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
+    if (pair_end <= pair_begin) return hipSuccess;
+    hipLaunchKernelGGL(k_heavy_gram_bf16, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
+                       a, pair_begin, pair_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
+    if (pair_end <= pair_begin) return hipSuccess;
+    if (a.fp64res)
+        hipLaunchKernelGGL(k_heavy_resid<true>, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0,
+                           s, a, pair_begin, pair_end);
+    else
+        hipLaunchKernelGGL(k_heavy_resid<false>, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64),
+                           0, s, a, pair_begin, pair_end);
+    return hipGetLastError();
+}
 
 hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;

@@ -97,8 +97,8 @@ struct Side {
 
 // Device-side counters of per-row events (cleared before each half-sweep).
 // Kernel groups timed by als_profile_begin / als_profile_end, per side.
-constexpr int NPROF = 10;
-enum ProfSlot : int { PROF_HSELECT = 7, PROF_HGRAM = 8, PROF_HSOLVE = 9 };
+constexpr int NPROF = 12;
+enum ProfSlot : int { PROF_HSELECT = 7, PROF_HGRAM = 8, PROF_HSOLVE = 9, PROF_HRESID = 10, PROF_HREFINE = 11 };
 
 enum StatSlot : int { ST_EMPTY = 0, ST_FALLBACK = 1, ST_FP64RES = 2, ST_ROWS = 3, NSTATS = 8 };
 
@@ -137,6 +137,9 @@ struct HeavyArgs {
     int32_t *cutT;
     int32_t *cutK;
     float *partials;
+    double *resid;            // [pair_cap * 64] refinement residual partials
+    int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
+    int32_t fp64res;          // residual accumulated in FP64
     unsigned long long *stats;
 };
 
@@ -164,6 +167,8 @@ hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_
 hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
                               hipStream_t s);
+hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
+hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 
 // launchers (setup.hip)
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
@@ -200,10 +205,13 @@ struct als_ctx {
     unsigned long long *stats = nullptr;  // [NSTATS]
     double *obj_partials = nullptr;
     double *obj_out = nullptr;            // [4]
-    float *partials = nullptr;            // [PAIR_CAP * (NF + 1) * 64]
+    float *partials = nullptr;            // [pair_cap * (NF + 1) * 64]
+    double *resid = nullptr;              // [pair_cap * 64]
     int32_t heavy_n = coreals::DEFAULT_HEAVY_N;
     int32_t chunk = coreals::DEFAULT_CHUNK;
     int64_t pair_cap = coreals::PAIR_CAP;
+    bool bf16 = false;     // heavy-row Gram on bf16 MFMA + one refinement step
+    bool fp64res = false;  // refinement residual in FP64
     void *temp = nullptr;
     size_t temp_bytes = 0;
     std::string err;

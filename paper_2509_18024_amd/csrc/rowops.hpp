@@ -44,7 +44,8 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 struct alignas(16) WaveLds {
     float X[CK][NF + 4];      // staged design rows (select, Gram)
     float y[CK];
-    float urhs[NF];           // solve: solution components parked by the back substitution
+    float urhs[2 * NF];       // solve: solution components parked by the back substitution
+    double rres[CK];          // refinement: residuals y_k - x_k . u of the staged rows
 };
 
 // Largest value over the wave of a non-negative-or-(-1) integer key: DPP
@@ -229,9 +230,9 @@ __device__ __forceinline__ void finish_system(float (&A)[NF], float &rhs, float 
 // largest |entry| among rows not yet used, found by a DPP max); otherwise
 // row J is the pivot (symmetric positive definite systems).  The pivot row
 // reaches the other lanes through scalar broadcasts (v_readlane).
-template <bool PIVOT, int J>
-__device__ __forceinline__ void elim_step_u(float (&A)[NF], float &rhs, int lane, int nf, float tol, int &my_step,
-                                            bool &ok) {
+template <bool PIVOT, int NR, int J>
+__device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
+                                            int &my_step, bool &ok) {
     int p;
     bool active;
     if constexpr (PIVOT) {
@@ -252,11 +253,13 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float &rhs, int lane
     if (lane == p) my_step = J;
 #pragma unroll
     for (int c = J + 1; c < NF; ++c) A[c] = fmaf(-l, readlane_f(A[c], p), A[c]);
-    rhs = fmaf(-l, readlane_f(rhs, p), rhs);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) rhs[q] = fmaf(-l, readlane_f(rhs[q], p), rhs[q]);
 }
 
-template <bool PIVOT, int J>
-__device__ __forceinline__ void back_step_u(const float (&A)[NF], float &rhs, int lane, int my_step, float *xs) {
+template <bool PIVOT, int NR, int J>
+__device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[NR], int lane, int my_step,
+                                            float *xs) {
     int p;
     if constexpr (PIVOT) {
         const uint64_t bal = __ballot(my_step == J);
@@ -265,39 +268,55 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float &rhs, in
     } else {
         p = J;
     }
-    const float x = readlane_f(rhs, p) / readlane_f(A[J], p);
-    if (lane == p) xs[J] = x;
-    if (my_step < J) rhs = fmaf(-A[J], x, rhs);
+    const float d = readlane_f(A[J], p);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const float x = readlane_f(rhs[q], p) / d;
+        if (lane == p) xs[q * NF + J] = x;
+        if (my_step < J) rhs[q] = fmaf(-A[J], x, rhs[q]);
+    }
 }
 
-template <bool PIVOT, int... J>
-__device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float &rhs, int lane,
-                                           int nf, float tol, int &my_step, bool &ok) {
-    (elim_step_u<PIVOT, J>(A, rhs, lane, nf, tol, my_step, ok), ...);
+template <bool PIVOT, int NR, int... J>
+__device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR],
+                                           int lane, int nf, float tol, int &my_step, bool &ok) {
+    (elim_step_u<PIVOT, NR, J>(A, rhs, lane, nf, tol, my_step, ok), ...);
 }
 
-template <bool PIVOT, int... J>
-__device__ __forceinline__ void back_all_u(std::integer_sequence<int, J...>, const float (&A)[NF], float &rhs,
-                                           int lane, int my_step, float *xs) {
-    (back_step_u<PIVOT, NF - 1 - J>(A, rhs, lane, my_step, xs), ...);
+template <bool PIVOT, int NR, int... J>
+__device__ __forceinline__ void back_all_u(std::integer_sequence<int, J...>, const float (&A)[NF],
+                                           float (&rhs)[NR], int lane, int my_step, float *xs) {
+    (back_step_u<PIVOT, NR, NF - 1 - J>(A, rhs, lane, my_step, xs), ...);
 }
 
-// Solve the register-resident system; returns false when a pivot of the first
-// nf steps is <= tol.  On success u holds solution component `lane`.
-template <bool PIVOT>
-__device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
-                                      WaveLds &L) {
+// Solve the register-resident system for NR right-hand sides at once; returns
+// false when a pivot of the first nf steps is <= tol.  On success x[q] holds
+// component `lane` of the solution for right-hand side q.
+template <bool PIVOT, int NR>
+__device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
+                                        float (&x)[NR], WaveLds &L) {
     int my_step = NF;  // elimination step at which this lane's row was the pivot
     bool ok = true;
-    elim_all_u<PIVOT>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    elim_all_u<PIVOT, NR>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
     if (!PIVOT) my_step = lane;
     if (!ok) return false;
     wave_sync();
-    back_all_u<PIVOT>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, my_step, L.urhs);
+    back_all_u<PIVOT, NR>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, my_step, L.urhs);
     wave_sync();
-    u = L.urhs[lane];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) x[q] = L.urhs[q * NF + lane];
     wave_sync();
     return true;
+}
+
+template <bool PIVOT>
+__device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
+                                      WaveLds &L) {
+    float r[1] = {rhs};
+    float x[1];
+    const bool ok = solve_n<PIVOT, 1>(A, r, lane, nf, tol, x, L);
+    if (ok) u = x[0];
+    return ok;
 }
 
 __device__ __forceinline__ float system_tol(const float (&A)[NF], int nf) {

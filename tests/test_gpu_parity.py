@@ -387,3 +387,40 @@ def test_wide_row_selection_and_sweep(ora):
     Uo, _ = ora.half_sweep(rp, ci, val, M0.astype(np.float64), 0.05, 1, 10, 1)
     assert rel_fro(U.cpu().numpy(), Uo) <= 1e-4
     als.close()
+
+
+@gpu
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("which", range(3))
+def test_bf16_refined_heavy_rows(ora, which, prec):
+    """BF16 MFMA Gram on heavy rows + one refinement step (FP32 or FP64
+    residual) against the FP64 oracle.  Parity with the oracle is not fixed by
+    the paper for this precision; the bound follows from the arithmetic: bf16
+    operands carry a relative error up to 2^-9, so the first solve is off by
+    about kappa 2^-8 and one refinement step multiplies that by about kappa 2^-8
+    again.  With kappa 2^-8 << 1 on these systems the refined factors meet the
+    same 1e-4 bound as the FP32 path.  Measured errors are printed per factor
+    matrix."""
+    import torch
+    name, p = heavy_cases()[which]
+    note(f"[bf16 prec={prec}] {name}")
+    als = make_als(p, precision=prec, **HEAVY_KW)
+    M = torch.from_numpy(p.M0).cuda()
+    U, st = als.half_sweep_users(M, stats=True)
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), p.lam,
+                           p.budget_num, p.budget_den, p.min_keep)
+    eu = rel_fro(U.cpu().numpy(), Uo)
+    U32 = Uo.astype(np.float32)
+    Mg, st2 = als.half_sweep_items(torch.from_numpy(U32).cuda(), stats=True)
+    torch.cuda.synchronize()
+    cp, ri, vt = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+    Mo, _ = ora.half_sweep(cp, ri, vt, U32.astype(np.float64), p.lam, p.budget_num, p.budget_den,
+                           p.min_keep)
+    em = rel_fro(Mg.cpu().numpy(), Mo)
+    note(f"  users rel err {eu:.3e} items rel err {em:.3e} fp64-residual rows {st.n_fp64_residual}"
+         f"/{st2.n_fp64_residual}")
+    assert eu <= 1e-4 and em <= 1e-4
+    if prec == 2:
+        assert st.n_fp64_residual + st2.n_fp64_residual > 0
+    als.close()
