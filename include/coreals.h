@@ -81,6 +81,9 @@ typedef struct {
     int32_t heavy_chunk;         /* entries per partial Gram of such rows; 0 = 1024 */
     int32_t heavy_pair_cap;      /* partial systems kept in scratch at once (sizes the
                                     workspace); 0 = 32768 */
+    int32_t light_blocks;        /* grid of the persistent light-row kernels, whose
+                                    wavefronts take rows from an atomic counter;
+                                    0 = one row per wavefront */
 } als_problem;
 
 typedef struct {
@@ -154,6 +157,12 @@ als_status objective(als_ctx *c, const float *U, const float *M, als_objective *
  * solves.  Either array may be NULL.  Profiling then stops. */
 als_status als_profile_begin(als_ctx *c);
 als_status als_profile_end(als_ctx *c, double *ms, int64_t *launches);
+
+/* Capture each half-sweep into a HIP graph on its first call and replay the
+ * graph on later calls with the same factor pointers (a call with other
+ * pointers captures a new graph).  Needs a non-default stream (ALS_E_STATE
+ * otherwise).  Profiling calls are never captured. */
+als_status als_use_graphs(als_ctx *c, int enable);
 
 /* Row counts of the degree classes (host out[side*8 + cls]); no device call. */
 als_status als_class_counts(const als_ctx *c, int64_t *out);

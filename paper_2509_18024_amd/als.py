@@ -32,7 +32,8 @@ class CoreALS:
     def __init__(self, n_u: int, n_m: int, n_f: int, row_ptr: torch.Tensor, col_idx: torch.Tensor,
                  val: torch.Tensor, lam: float, budget: Tuple[int, int] = (1, 1), min_keep: int = 1,
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
-                 heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0):
+                 heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
+                 light_blocks: int = 0, graphs: bool = False):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -54,6 +55,7 @@ class CoreALS:
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)
         p.heavy_pair_cap = int(heavy_pair_cap)
+        p.light_blocks = int(light_blocks)
         size = capi.als_workspace_size(p)
         if size == 0:
             raise capi.ALSError(capi.ALS_E_ARG, "invalid problem sizes")
@@ -61,6 +63,8 @@ class CoreALS:
         p.workspace, p.workspace_bytes = self.workspace.data_ptr(), size
         self.problem = p
         self.ctx = capi.als_init(p)
+        if graphs:
+            capi.als_use_graphs(self.ctx, True)
 
     @classmethod
     def from_problem(cls, prob, device="cuda", budget=None, precision=capi.ALS_PREC_FP32, **kw):

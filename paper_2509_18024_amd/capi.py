@@ -32,7 +32,7 @@ class als_problem(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("heavy_min_degree", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
-        ("heavy_pair_cap", ctypes.c_int32),
+        ("heavy_pair_cap", ctypes.c_int32), ("light_blocks", ctypes.c_int32),
     ]
 
 
@@ -56,7 +56,7 @@ _lib = None
 
 EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_items",
            "core_select_count", "core_select", "objective", "als_profile_begin", "als_profile_end",
-           "als_class_counts", "als_destroy", "als_last_error"]
+           "als_class_counts", "als_use_graphs", "als_destroy", "als_last_error"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
 NPROF = 12
@@ -94,6 +94,8 @@ def load():
     L.als_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.als_class_counts.restype = i32
     L.als_class_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.als_use_graphs.restype = i32
+    L.als_use_graphs.argtypes = [vp, i32]
     L.als_destroy.restype = None
     L.als_destroy.argtypes = [vp]
     L.als_last_error.restype = ctypes.c_char_p
@@ -164,6 +166,10 @@ def als_class_counts(ctx):
     out = (ctypes.c_int64 * (2 * NCLASS))()
     _check(load().als_class_counts(ctx, out), ctx)
     return [list(out[:NCLASS]), list(out[NCLASS:])]
+
+
+def als_use_graphs(ctx, enable: bool) -> None:
+    _check(load().als_use_graphs(ctx, 1 if enable else 0), ctx)
 
 
 def als_destroy(ctx) -> None:

@@ -37,6 +37,7 @@ struct Layout {
     int32_t *perm_u;
     int32_t *perm_m;
     unsigned long long *stats;
+    unsigned int *queues;  // [2 * 16]
     int64_t *class_count;  // [2 * NCLASS]
     int64_t *max_deg;      // [2]
     int *err_flags;
@@ -86,6 +87,7 @@ Layout carve(const als_problem &p, void *base) {
     L.perm_u = c.take<int32_t>((size_t)p.n_u);
     L.perm_m = c.take<int32_t>((size_t)p.n_m);
     L.stats = c.take<unsigned long long>(NSTATS);
+    L.queues = c.take<unsigned int>(2 * 16);
     L.class_count = c.take<int64_t>(2 * NCLASS);
     L.max_deg = c.take<int64_t>(2);
     L.err_flags = c.take<int>(4);
@@ -132,12 +134,14 @@ als_status fail(als_ctx *c, als_status st, const char *fmt, const char *detail =
         if (e_ != hipSuccess) return fail((ctx), ALS_E_DEVICE, "HIP error: %s", hipGetErrorString(e_)); \
     } while (0)
 
-als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st) {
-    if (!c) return ALS_E_STATE;
-    if (!other || !out) return fail(c, ALS_E_ARG, "NULL factor pointer%s");
-    if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
+// All launches of one half-sweep, in stream order (also what a graph captures).
+als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *out) {
     const Side &S = c->side[side];
-    HIP_CHECK(c, hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * NSTATS, c->stream));
+    unsigned int *queues = c->queues + side * 16;
+    // counters are cleared by a kernel, not a memset node, so that replays of a
+    // captured graph start from zero every time
+    HIP_CHECK(c, launch_zero_u64(c->stats, NSTATS, c->stream));
+    HIP_CHECK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(queues), 8, c->stream));
     auto mark_begin = [&](int cls, als_ctx::Mark &mk) -> hipError_t {
         if (!c->profiling) return hipSuccess;
         hipError_t e = hipEventCreate(&mk.start);
@@ -168,10 +172,11 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         a.den = c->p.budget_den;
         a.min_keep = c->p.min_keep;
         a.stats = c->stats;
+        a.queue = queues + cls;
         if (a.count <= 0) continue;
         als_ctx::Mark mk{};
         HIP_CHECK(c, mark_begin(cls, mk));
-        HIP_CHECK(c, launch_sweep_class(cls, a, c->stream));
+        HIP_CHECK(c, launch_sweep_class(cls, a, c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(mk));
     }
     const HeavyPlan &H = S.heavy;
@@ -201,6 +206,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         h.refine = 0;
         h.fp64res = c->fp64res ? 1 : 0;
         h.stats = c->stats;
+        h.queue = queues + CLS_HEAVY;
         if (c->p.budget_num < c->p.budget_den) {
             als_ctx::Mark mk{};
             HIP_CHECK(c, mark_begin(PROF_HSELECT, mk));
@@ -230,6 +236,40 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
             }
         }
     }
+    return ALS_OK;
+}
+
+als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st) {
+    if (!c) return ALS_E_STATE;
+    if (!other || !out) return fail(c, ALS_E_ARG, "NULL factor pointer%s");
+    if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
+    if (c->use_graphs && !c->profiling) {
+        als_ctx::Graph &G = c->graph[side];
+        if (!G.exec || G.other != other || G.out != out) {
+            if (G.exec) {
+                (void)hipGraphExecDestroy(G.exec);
+                G.exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            als_status rs = enqueue_half_sweep(c, side, other, out);
+            hipError_t ec = hipStreamEndCapture(c->stream, &g);
+            if (rs != ALS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rs;
+            }
+            HIP_CHECK(c, ec);
+            hipError_t ei = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_CHECK(c, ei);
+            G.other = other;
+            G.out = out;
+        }
+        HIP_CHECK(c, hipGraphLaunch(G.exec, c->stream));
+    } else {
+        als_status rs = enqueue_half_sweep(c, side, other, out);
+        if (rs != ALS_OK) return rs;
+    }
     if (st) {
         unsigned long long h[NSTATS];
         HIP_CHECK(c, hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -237,7 +277,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         st->n_empty = (int64_t)h[ST_EMPTY];
         st->n_singular_fallback = (int64_t)h[ST_FALLBACK];
         st->n_fp64_residual = (int64_t)h[ST_FP64RES];
-        st->n_rows = S.n_rows;
+        st->n_rows = c->side[side].n_rows;
     }
     return ALS_OK;
 }
@@ -276,6 +316,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->row_idx = L.row_idx;
     c->val_t = L.val_t;
     c->stats = L.stats;
+    c->queues = L.queues;
+    c->light_blocks = p->light_blocks;
     c->obj_partials = L.obj_partials;
     c->obj_out = L.obj_out;
     c->partials = L.partials;
@@ -531,8 +573,18 @@ als_status als_class_counts(const als_ctx *c, int64_t *out) {
     return ALS_OK;
 }
 
+als_status als_use_graphs(als_ctx *c, int enable) {
+    if (!c) return ALS_E_STATE;
+    if (enable && c->stream == nullptr)
+        return fail(c, ALS_E_STATE, "graph capture needs a non-default stream%s");
+    c->use_graphs = enable != 0;
+    return ALS_OK;
+}
+
 void als_destroy(als_ctx *c) {
     if (!c) return;
+    for (auto &g : c->graph)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (auto &m : c->marks) {
         (void)hipEventDestroy(m.start);
         (void)hipEventDestroy(m.stop);

@@ -139,12 +139,26 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
     const int w = tid >> 6;
     const int lane = tid & 63;
     const int nf = a.nf;
-    for (int64_t t = blockIdx.x; t < a.count; t += gridDim.x) {
+    __shared__ int64_t next_t;
+    int64_t t = blockIdx.x;
+    for (;;) {
+        // rows of very different degree: workgroups take the next row from a
+        // counter when one is given, else a grid-stride order
+        if (a.queue) {
+            if (tid == 0) next_t = (int64_t)atomicAdd(a.queue, 1u);
+            __syncthreads();
+            t = next_t;
+            __syncthreads();
+        }
+        if (t >= a.count) break;
         const int64_t i = a.rows ? (int64_t)a.rows[t] : row_begin + t;
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
-        if (!is_heavy_core(n, s, a.heavy_n)) continue;  // uniform over the workgroup
+        if (!is_heavy_core(n, s, a.heavy_n)) {  // uniform over the workgroup
+            if (!a.queue) t += gridDim.x;
+            continue;
+        }
         const bool wide = n >= 65536;
         if (tid < 64) {
             S.prefix[tid] = 0;
@@ -273,6 +287,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
             a.cutK[t * 64 + tid] = S.K[tid];
         }
         __syncthreads();
+        if (!a.queue) t += gridDim.x;
     }
 }
 

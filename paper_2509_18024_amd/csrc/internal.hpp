@@ -115,6 +115,7 @@ struct SweepArgs {
     uint32_t num, den;
     int32_t min_keep;
     unsigned long long *stats;
+    unsigned int *queue;     // row counter of this class (persistent launch)
 };
 
 struct HeavyArgs {
@@ -141,6 +142,7 @@ struct HeavyArgs {
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
     int32_t fp64res;          // residual accumulated in FP64
     unsigned long long *stats;
+    unsigned int *queue;      // heavy-row selection counter (nullptr: grid-stride)
 };
 
 struct SelectArgs {
@@ -159,7 +161,7 @@ struct SelectArgs {
 };
 
 // launchers (sweep.hip)
-hipError_t launch_sweep_class(int cls, const SweepArgs &a, hipStream_t s);
+hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 
 // launchers (heavy.hip)
@@ -171,6 +173,7 @@ hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_
 hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 
 // launchers (setup.hip)
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
 size_t perm_temp_bytes(int64_t n_rows);
 hipError_t launch_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *ptr,
@@ -210,6 +213,7 @@ struct als_ctx {
     int32_t heavy_n = coreals::DEFAULT_HEAVY_N;
     int32_t chunk = coreals::DEFAULT_CHUNK;
     int64_t pair_cap = coreals::PAIR_CAP;
+    int32_t light_blocks = 0;  // grid of the persistent light-row kernels (0: one row per wave)
     bool bf16 = false;     // heavy-row Gram on bf16 MFMA + one refinement step
     bool fp64res = false;  // refinement residual in FP64
     void *temp = nullptr;
@@ -222,4 +226,13 @@ struct als_ctx {
     };
     bool profiling = false;
     std::vector<Mark> marks;
+    // HIP graphs of the two half-sweeps, keyed by the factor pointers
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        const float *other = nullptr;
+        float *out = nullptr;
+    };
+    bool use_graphs = false;
+    Graph graph[2];
+    unsigned int *queues = nullptr;  // [2 * 16] row counters
 };

@@ -295,7 +295,17 @@ unsigned grid_for(int64_t n, int threads) {
     return (unsigned)g;
 }
 
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    for (int q = threadIdx.x; q < n; q += blockDim.x) p[q] = 0ull;
+}
+
 }  // namespace
+
+// Clears counters with a kernel (safe inside a captured HIP graph).
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
 
 size_t csc_temp_bytes(int64_t nnz, int64_t n_cols) {
     size_t n = (size_t)(nnz > 0 ? nnz : 1);

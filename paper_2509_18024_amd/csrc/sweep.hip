@@ -28,14 +28,20 @@ __device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, in
 }
 
 template <int CLS>
-__global__ __launch_bounds__(WPB * 64) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     __shared__ WaveLds lds[WPB];
     const int w = threadIdx.x >> 6;
     const int lane0 = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
 
-    for (int64_t slot = (int64_t)blockIdx.x * WPB + w; slot < a.count; slot += (int64_t)gridDim.x * WPB) {
+    // persistent launch: each wavefront takes the next row of the class from
+    // an atomic counter (rows are ordered by decreasing degree)
+    for (;;) {
+        unsigned int got = 0;
+        if (lane0 == 0) got = atomicAdd(a.queue, 1u);
+        const int64_t slot = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)got);
+        if (slot >= a.count) break;
         const int lane = opaque_lane(lane0);
         const int64_t i = a.perm[slot];
         const int64_t beg = a.ptr[i];
@@ -72,6 +78,16 @@ __global__ __launch_bounds__(WPB * 64) void k_sweep(SweepArgs a) {
         }
         if (lane < a.nf) a.out[i * a.nf + lane] = u;
     }
+}
+
+// Full-data light rows (LDL^T, no pivot search): fits two waves per SIMD as is.
+__global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL>(a); }
+
+// Core light rows: the pivot search raises register demand; capping the
+// kernel at two waves per SIMD (a few spills) beats one wave per SIMD.
+template <int CLS>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
+    sweep_rows<CLS>(a);
 }
 
 // CES positions for a contiguous row range (the core_select entry point).
@@ -122,25 +138,29 @@ __global__ __launch_bounds__(WPB * 64) void k_select(SelectArgs a) {
 }
 
 template <int CLS>
-hipError_t launch_one(const SweepArgs &a, hipStream_t s) {
+hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
     int64_t blocks = (a.count + WPB - 1) / WPB;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     if (blocks > 256 * 64) blocks = 256 * 64;
-    hipLaunchKernelGGL(k_sweep<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    if constexpr (CLS == CLS_FULL)
+        hipLaunchKernelGGL(k_sweep_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sweep_class(int cls, const SweepArgs &a, hipStream_t s) {
+hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;
     switch (cls) {
-        case CLS_FULL: return launch_one<CLS_FULL>(a, s);
-        case CLS_NET1: return launch_one<CLS_NET1>(a, s);
-        case CLS_NET2: return launch_one<CLS_NET2>(a, s);
-        case CLS_NET4: return launch_one<CLS_NET4>(a, s);
-        case CLS_NET8: return launch_one<CLS_NET8>(a, s);
-        case CLS_NET16: return launch_one<CLS_NET16>(a, s);
-        case CLS_NET32: return launch_one<CLS_NET32>(a, s);
+        case CLS_FULL: return launch_one<CLS_FULL>(a, max_blocks, s);
+        case CLS_NET1: return launch_one<CLS_NET1>(a, max_blocks, s);
+        case CLS_NET2: return launch_one<CLS_NET2>(a, max_blocks, s);
+        case CLS_NET4: return launch_one<CLS_NET4>(a, max_blocks, s);
+        case CLS_NET8: return launch_one<CLS_NET8>(a, max_blocks, s);
+        case CLS_NET16: return launch_one<CLS_NET16>(a, max_blocks, s);
+        case CLS_NET32: return launch_one<CLS_NET32>(a, max_blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
