@@ -83,44 +83,64 @@ def class_work(deg, num, den, min_keep, nf, heavy_n=1024):
     return out
 
 
-def time_variant(torch, CoreALS, run_als, prob, dev, budget, steps, warmup, tag, precision=0):
+def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, precision=0, cfg=None):
+    """Time `steps` sweeps (users + items half-sweep) after `warmup` untimed
+    ones, on the context's own stream: once as eager launches with per-kernel
+    HIP events (the timed region), once as HIP-graph replays."""
     from paper_2509_18024_amd import capi
+    from paper_2509_18024_amd.als import CoreALS
+    cfg = cfg or {}
+    rp, ci, v = gpu_csr
     t0 = time.time()
-    als = CoreALS.from_problem(prob, dev, budget=budget, precision=precision)
-    torch.cuda.synchronize()
-    init_s = time.time() - t0
-    counts = capi.als_class_counts(als.ctx)
-    M = torch.from_numpy(prob.M0).to(dev)
-    U = torch.empty(prob.n_u, prob.n_f, dtype=torch.float32, device=dev)
-    for _ in range(warmup):
-        als.half_sweep_users(M, U)
-        als.half_sweep_items(U, M)
-    torch.cuda.synchronize()
-    stream = als.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    capi.als_profile_begin(als.ctx)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    wall0 = time.perf_counter()
-    for _ in range(steps):
-        als.half_sweep_users(M, U)
-        als.half_sweep_items(U, M)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = ev0.elapsed_time(ev1)
-    kms, klaunch = capi.als_profile_end(als.ctx)
-    obj = als.objective(U, M)
+    with torch.cuda.stream(stream):
+        als = CoreALS(prob.n_u, prob.n_m, prob.n_f, rp, ci, v, prob.lam, budget, prob.min_keep, precision,
+                      stream=stream, graphs=True, **cfg)
+        stream.synchronize()
+        init_s = time.time() - t0
+        counts = capi.als_class_counts(als.ctx)
+        M = torch.from_numpy(prob.M0).to(rp.device)
+        U = torch.empty(prob.n_u, prob.n_f, dtype=torch.float32, device=rp.device)
+        for _ in range(warmup):
+            als.half_sweep_users(M, U)
+            als.half_sweep_items(U, M)
+        stream.synchronize()
+        # timed region: eager launches with a HIP event pair around every
+        # kernel group (recorded by the library on this stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        capi.als_profile_begin(als.ctx)
+        ev0.record(stream)
+        wall0 = time.perf_counter()
+        for _ in range(steps):
+            als.half_sweep_users(M, U)
+            als.half_sweep_items(U, M)
+        ev1.record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_total = ev0.elapsed_time(ev1)
+        kms, klaunch = capi.als_profile_end(als.ctx)
+        # the same sweeps replayed from the captured HIP graphs
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(steps):
+            als.half_sweep_users(M, U)
+            als.half_sweep_items(U, M)
+        g1.record(stream)
+        stream.synchronize()
+        graph_ms = g0.elapsed_time(g1) / steps
+        obj = als.objective(U, M)
     ms = ms_total / steps
     res = {
         "budget": f"{budget[0]}/{budget[1]}",
         "precision": ["fp32", "bf16+ir(fp32 residual)", "bf16+ir(fp64 residual)", "auto"][precision],
+        "schedule": cfg,
         "sweep_ms": ms,
         "sweep_s": ms / 1000.0,
         "solves_per_s": (prob.n_u + prob.n_m) / (ms / 1000.0),
         "wall_ms_per_step": 1000.0 * wall / steps,
-        "iterations_done": warmup + steps,
+        "graph_replay_ms_per_sweep": graph_ms,
+        "iterations_done": warmup + 2 * steps,
         "rmse": obj["rmse"],
         "remse": obj["remse"],
         "f": obj["f"],
@@ -128,9 +148,11 @@ def time_variant(torch, CoreALS, run_als, prob, dev, budget, steps, warmup, tag,
         "class_rows": counts,
         "kernel_ms": kms,
         "kernel_launches": klaunch,
+        "kernel_ms_sum_per_sweep": sum(sum(x) for x in kms) / steps,
     }
-    log(f"{tag}: r={res['budget']} sweep {ms:.3f} ms, {res['solves_per_s']:.3e} solves/s, "
-        f"rmse {obj['rmse']:.5f} after {warmup + steps} it, init {init_s:.2f}s")
+    log(f"{tag}: r={res['budget']} {res['precision']} sweep {ms:.3f} ms (graph replay {graph_ms:.3f}), "
+        f"{res['solves_per_s']:.3e} solves/s, "
+        f"rmse {obj['rmse']:.5f} after {warmup + 2 * steps} it, init {init_s:.2f}s, schedule {cfg}")
     return als, res
 
 
@@ -215,6 +237,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="time only r = 1/10 (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -223,7 +246,6 @@ def main():
 
     import torch
     from paper_2509_18024_amd import synth
-    from paper_2509_18024_amd.als import CoreALS, run_als
 
     dev = "cuda:0"
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -234,16 +256,41 @@ def main():
 
     # headline: core-elements ALS, r = 1/10, BF16 Gram + refinement (heavy rows);
     # comparator: plain full-data ALS in FP32 on the same GPU
+    from paper_2509_18024_amd import autotune
     HEAD = "core_r1/10_bf16ir"
     variants = [(HEAD, (1, 10), 1)]
     if not args.headline_only:
         variants += [("core_r1/10_fp32", (1, 10), 0), ("core_r1/20_bf16ir", (1, 20), 1),
                      ("core_r1/4_bf16ir", (1, 4), 1), ("full_fp32", (1, 1), 0),
                      ("full_bf16ir", (1, 1), 1)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gpu_csr = (torch.from_numpy(prob.row_ptr).to(dev), torch.from_numpy(prob.col_idx).to(dev),
+                   torch.from_numpy(prob.val).to(dev))
+    stream.synchronize()
+    # schedules: the committed tuning cache when it knows this problem, else a
+    # coordinate search on the box (written to gpurun_out/ for review)
+    tune_out = os.path.join(ROOT, "gpurun_out", "tuning_gfx950.json")
+    schedules = {}
+    for key, b, prec in [("core", (1, 10), 1), ("full", (1, 1), 0)]:
+        if args.no_tune:
+            schedules[key] = dict(autotune.DEFAULT)
+            continue
+        cached = autotune.load_cache()
+        sig = autotune.degree_signature(prob.row_ptr, prob.col_idx, prob.n_m)
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        ck = autotune.cache_key(arch, prob.n_f, prec, b, sig, prob.nnz)
+        if ck in cached:
+            schedules[key] = dict(cached[ck]["config"])
+            log(f"schedule {key}: tuning cache {schedules[key]}")
+        else:
+            os.makedirs(os.path.dirname(tune_out), exist_ok=True)
+            schedules[key] = autotune.tune(torch, prob, gpu_csr, b, prec, stream, log, path=tune_out)
     results = {}
     head_als = None
     for tag, b, prec in variants:
-        als, res = time_variant(torch, CoreALS, run_als, prob, dev, b, args.steps, args.warmup, tag, prec)
+        cfg = schedules["full" if b[0] == b[1] else "core"]
+        als, res = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg)
         results[tag] = res
         if tag == HEAD:
             head_als = als
@@ -256,8 +303,9 @@ def main():
     # roofline of the dominant kernel (largest summed time in the timed region)
     deg_u = np.diff(prob.row_ptr)
     deg_i = np.bincount(prob.col_idx, minlength=prob.n_m)
-    work = [class_work(deg_u, 1, 10, prob.min_keep, prob.n_f),
-            class_work(deg_i, 1, 10, prob.min_keep, prob.n_f)]
+    hn = head["schedule"].get("heavy_min_degree", 1024) or 1024
+    work = [class_work(deg_u, 1, 10, prob.min_keep, prob.n_f, hn),
+            class_work(deg_i, 1, 10, prob.min_keep, prob.n_f, hn)]
     for sd in range(2):
         for c in range(8):
             assert work[sd][c]["rows"] == head["class_rows"][sd][c], "class model mismatch"
@@ -292,7 +340,8 @@ def main():
     parity = None
     if not args.no_parity:
         log("sampled full-size parity against the oracle ...")
-        parity = sampled_parity(torch, head_als, prob, dev)
+        with torch.cuda.stream(stream):
+            parity = sampled_parity(torch, head_als, prob, dev)
         log(f"parity: {parity}")
     head_als.close()
 
