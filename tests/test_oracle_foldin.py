@@ -1,0 +1,61 @@
+"""Pins of the fold-in oracle: finite differences, GELU closed forms, a hand
+worked embedding bag and the AdamW update."""
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+from oracle import foldin
+
+
+def test_gelu_closed_forms():
+    assert foldin.gelu(np.array(0.0)) == 0.0
+    x = np.array([-3.0, -1.0, 0.5, 2.0])
+    np.testing.assert_allclose(foldin.gelu(x), x * norm.cdf(x), rtol=1e-14)
+    h = 1e-6
+    np.testing.assert_allclose(foldin.gelu_grad(x), (foldin.gelu(x + h) - foldin.gelu(x - h)) / (2 * h),
+                               rtol=1e-7)
+
+
+def test_bag_hand_example():
+    M = np.array([[1.0, 2.0], [3.0, -1.0], [0.0, 4.0]])
+    ptr = np.array([0, 2, 2, 3])
+    items = np.array([0, 2, 1])
+    vals = np.array([2.0, 1.0, 5.0])
+    b = foldin.bag(M, ptr, items, vals, [0, 1, 2])
+    np.testing.assert_allclose(b[0], [(2 * 1 + 1 * 0) / 2, (2 * 2 + 1 * 4) / 2])
+    assert np.all(b[1] == 0)
+    np.testing.assert_allclose(b[2], [15.0, -5.0])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_matches_central_differences(seed):
+    n_f, H, B = 5, 7, 4
+    rng = np.random.default_rng(seed)
+    theta = foldin.init_params(seed, n_f, H).astype(np.float64) + 0.1 * rng.standard_normal(
+        foldin.param_count(n_f, H))
+    x = rng.standard_normal((B, n_f))
+    tgt = rng.standard_normal((B, n_f))
+    L, g = foldin.loss_and_grad(theta, x, tgt, n_f, H)
+    eps = 1e-6
+    for k in rng.choice(len(theta), size=40, replace=False):
+        e = np.zeros_like(theta)
+        e[k] = eps
+        lp, _ = foldin.loss_and_grad(theta + e, x, tgt, n_f, H)
+        lm, _ = foldin.loss_and_grad(theta - e, x, tgt, n_f, H)
+        assert abs((lp - lm) / (2 * eps) - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
+
+
+def test_adamw_first_step_is_signed_lr():
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    t1, m, v = foldin.adamw(theta, g, np.zeros(3), np.zeros(3), 1, lr=0.01, wd=0.0)
+    # bias-corrected first step: m_hat / sqrt(v_hat) = sign(g) (up to eps)
+    np.testing.assert_allclose(t1, theta - 0.01 * np.sign(g), rtol=1e-5)
+    t2, _, _ = foldin.adamw(theta, np.zeros(3), np.zeros(3), np.zeros(3), 1, lr=0.01, wd=0.1)
+    np.testing.assert_allclose(t2, theta * (1 - 0.001))
+
+
+def test_param_count_matches_layer_sizes():
+    assert foldin.param_count(64, 256) == 64 * 256 + 256 + 256 * 256 + 256 + 256 * 64 + 64 == 98880
