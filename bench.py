@@ -227,6 +227,18 @@ def sampled_parity(torch, als, prob, dev, seed=11):
             "pass": bool(eu <= 1e-4 and em <= 1e-4)}
 
 
+def copy_calibration(torch, dev, nbytes=1 << 30, reps=3):
+    """A plain elementwise kernel (negation) that reads nbytes and writes nbytes
+    once per launch: the known-size reference for the HBM byte counters."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"kernel": "torch.neg float32", "read_bytes": nbytes,
+                                           "write_bytes": nbytes, "launches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +250,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="time only r = 1/10 (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB float32 read+write kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -249,6 +263,9 @@ def main():
 
     dev = "cuda:0"
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+        return
     t = time.time()
     log(f"generating c3_batched (scale {args.scale}) ...")
     prob = synth.c3_batched(scale=args.scale)

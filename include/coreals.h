@@ -59,7 +59,11 @@ typedef enum {
                                      lambda < 1e-3, FP32 residual otherwise   */
 } als_precision;
 
-#define ALS_VALIDATE 1u /* check ratings for NaN/Inf in als_init */
+#define ALS_VALIDATE 1u   /* check ratings for NaN/Inf in als_init */
+#define ALS_USERS_ONLY 2u /* users side only: no column view is built, and
+                             half_sweep_items, core_select(side 1) and objective
+                             return ALS_E_STATE (contexts of new users to fold
+                             in, see foldin_answer) */
 
 typedef struct {
     int64_t n_u, n_m, nnz;
@@ -72,7 +76,7 @@ typedef struct {
     uint32_t budget_den;         /* 0 < r <= 1; r = 1 is full-data ALS              */
     int32_t min_keep;            /* s_i = min(n_i, max(min_keep, floor(n_i r)))     */
     int32_t precision;           /* als_precision                                   */
-    uint32_t flags;              /* ALS_VALIDATE                                    */
+    uint32_t flags;              /* ALS_VALIDATE | ALS_USERS_ONLY                   */
     void *stream;                /* hipStream_t                                     */
     void *workspace;             /* device buffer, at least als_workspace_size bytes */
     size_t workspace_bytes;
@@ -169,6 +173,112 @@ als_status als_class_counts(const als_ctx *c, int64_t *out);
 
 /* Release the context (host memory only; the caller frees its buffers). */
 void als_destroy(als_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * Learned fold-in of new users.  Beyond the method itself: a small network
+ * answers a new user (ratings on the trained items, M frozen) from the
+ * embedding bag b = (1/d) sum_k r_k M[j_k] of its d ratings:
+ *     h1 = GELU(W1 b + c1), h2 = GELU(W2 h1 + c2), u = W3 h2 + c3,
+ * GELU(x) = x Phi(x).  It is trained on factor rows that ALS produced, and an
+ * answer is kept only when the relative residual |b_i - A_i u| / |b_i| of the
+ * user's own regression (A_i u = b_i: eq. core_ui at the context's rate,
+ * eq. (U) when r = 1) is within a tolerance; otherwise that regression is
+ * solved exactly (one direct solve, as in a users half-sweep).
+ *
+ * Parameters are one float vector of foldin_param_count(n_f, hidden) entries:
+ * W1 [hidden x n_f], c1 [hidden], W2 [hidden x hidden], c2 [hidden],
+ * W3 [n_f x hidden], c3 [n_f], each row-major.  FP32 master weights; matrix
+ * products on MFMA with bf16 operands and FP32 accumulation (FOLDIN_BF16) or
+ * FP32 operands (FOLDIN_FP32).  All calls run on cfg.stream (foldin_answer:
+ * on the query context's stream) and are asynchronous unless marked "syncs".
+ * ---------------------------------------------------------------------- */
+typedef struct foldin_model foldin_model;
+
+typedef enum { FOLDIN_BF16 = 0, FOLDIN_FP32 = 1 } foldin_precision;
+
+typedef struct {
+    int32_t n_f;            /* input and output width, 1..64                    */
+    int32_t hidden;         /* hidden width, 1..1024                           */
+    int32_t max_batch;      /* most rows per forward / gradient batch, 1..2^20 */
+    int32_t precision;      /* foldin_precision                                 */
+    int64_t max_train_rows; /* most rows foldin_train may shuffle (sizes the workspace) */
+    float lr, beta1, beta2, eps, weight_decay;   /* AdamW (decoupled decay)     */
+    void *stream;           /* hipStream_t                                      */
+    void *workspace;        /* device buffer of foldin_workspace_size bytes; holds the
+                               weights, AdamW moments, activations and gradients */
+    size_t workspace_bytes;
+} foldin_cfg;
+
+typedef struct {
+    int64_t n_rows;              /* users answered                                 */
+    int64_t n_mlp;               /* answers of the network kept                    */
+    int64_t n_exact;             /* users solved exactly (residual above tol, or no
+                                    ratings: answer 0)                             */
+    int64_t n_empty;             /* users without ratings                          */
+    int64_t n_singular_fallback; /* exact solves whose core system was singular and
+                                    used the full-data update eq. (U) instead      */
+} foldin_answer_stats;
+
+/* Number of parameters (0 for invalid sizes).  Host only. */
+int64_t foldin_param_count(int32_t n_f, int32_t hidden);
+
+/* Workspace bytes for cfg (0 if cfg is invalid).  Host only. */
+size_t foldin_workspace_size(const foldin_cfg *cfg);
+
+/* Create a model in cfg->workspace with initial weights `params` (device,
+ * copied) and zero AdamW moments.  ALS_E_ARG for invalid sizes, ALS_E_NOMEM if
+ * the workspace is too small. */
+als_status foldin_create(const foldin_cfg *cfg, const float *params, foldin_model **out);
+
+/* Copy the current weights to params (device), or replace them (moments and
+ * step count reset). */
+als_status foldin_get_params(foldin_model *m, float *params);
+als_status foldin_set_params(foldin_model *m, const float *params);
+
+/* Network answers for n users: U_out[b] for user rows[b] (rows: device int32
+ * [n], or NULL for users 0..n-1) of the CSR (ptr, items, vals) over the items
+ * of M [n_items x n_f].  U_out: device [n * n_f].  The CSR and rows are not
+ * checked here: they must be valid as als_init checks them (monotone ptr,
+ * item indices below n_items, row ids inside the CSR). */
+als_status foldin_forward(foldin_model *m, const float *M, const int64_t *ptr, const int32_t *items,
+                          const float *vals, const int32_t *rows, int64_t n, float *U_out);
+
+/* Forward and backward pass of one batch (1..max_batch rows, as in
+ * foldin_forward) against target rows target[rows[b]] ([* x n_f], device):
+ * loss = mean over the batch and the n_f outputs of (u - target)^2.  Writes the
+ * gradient of the loss (device [param_count], optional) and the loss (device
+ * float, optional). */
+als_status foldin_grad(foldin_model *m, const float *M, const int64_t *ptr, const int32_t *items,
+                       const float *vals, const int32_t *rows, int64_t n, const float *target, float *grad,
+                       float *loss);
+
+/* One AdamW step with gradient grad (device [param_count]), or with the
+ * gradient of the last foldin_grad when grad is NULL. */
+als_status foldin_adamw(foldin_model *m, const float *grad);
+
+/* Train for `epochs` passes over rows 0..n_rows-1 of the CSR, in batches of
+ * `batch` rows shuffled per epoch by a splitmix64 stream seeded with `seed`;
+ * one AdamW step per batch.  loss_per_epoch (host [epochs], optional): mean
+ * batch loss of each epoch.  Syncs once per epoch. */
+als_status foldin_train(foldin_model *m, const float *M, const int64_t *ptr, const int32_t *items,
+                        const float *vals, int64_t n_rows, const float *target, int32_t epochs, int32_t batch,
+                        uint64_t seed, float *loss_per_epoch);
+
+/* Answer the users of the query context q (its CSR holds the new users'
+ * ratings over the n_m items of M; create it with ALS_USERS_ONLY and the
+ * lambda, rate and precision the exact regressions should use).  Writes
+ * U_new [n_u x n_f] (device): the network's answer where the relative
+ * residual rho[i] (device float [n_u]) of user i's regression is <= tol, the
+ * exact solution otherwise; path[i] (device int32 [n_u]) = 0 for a kept
+ * answer, 1 for an exact one.  st (host, optional) makes the call sync. */
+als_status foldin_answer(als_ctx *q, foldin_model *m, const float *M, double tol, float *U_new, int32_t *path,
+                         float *rho, foldin_answer_stats *st);
+
+/* Release the model (host memory only). */
+void foldin_destroy(foldin_model *m);
+
+/* Message of the last failure on m. */
+const char *foldin_last_error(const foldin_model *m);
 
 /* Message of the last failure on c (or of the last failed als_init when c is
  * NULL).  Valid until the next call on the same context. */

@@ -104,14 +104,27 @@ def adamw(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
     return theta, m, v
 
 
-def init_params(seed: int, n_f: int, hidden: int) -> np.ndarray:
-    """Seeded initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)), zero biases."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for name, shp in shapes(n_f, hidden):
-        if name.startswith("W"):
-            lim = 1.0 / math.sqrt(shp[1])
-            parts.append(rng.uniform(-lim, lim, size=shp).ravel())
-        else:
-            parts.append(np.zeros(shp).ravel())
-    return np.concatenate(parts).astype(np.float32)
+def core_system(X, y, lam, s):
+    """A = X*^T X + lam n E and b = X*^T y of one row (eq. core_ui; eq. (U) when
+    s = n), with X* the CES sketch of Algorithm 1 (the C oracle's selection)."""
+    from . import select
+    X = np.asarray(X, np.float64)
+    y = np.asarray(y, np.float64)
+    n, nf = X.shape
+    W = np.zeros_like(X)
+    if s >= n:
+        W[:] = X
+    elif s > 0:
+        pos = select(X, s)
+        for a in range(nf):
+            W[pos[a], a] = X[pos[a], a]
+    return W.T @ X + lam * n * np.eye(nf), W.T @ y
+
+
+def relative_residual(X, y, lam, s, u):
+    """|b - A u| / |b| of the row's system; inf when b = 0 (Section 3 estimator)."""
+    A, b = core_system(X, y, lam, s)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return math.inf
+    return float(np.linalg.norm(b - A @ np.asarray(u, np.float64)) / nb)

@@ -3,6 +3,8 @@
 Only marshalling happens here (shape/dtype/device checks, pointer passing);
 all computation runs in libcoreals.so.  The ALS driver alternates the two
 half-sweeps in the order of Algorithm 2 (users from M, then items from U).
+FoldIn wraps the learned fold-in model (network answers for new users, kept
+when the residual of the user's regression is small, exact solves otherwise).
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ class CoreALS:
                  val: torch.Tensor, lam: float, budget: Tuple[int, int] = (1, 1), min_keep: int = 1,
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
-                 light_blocks: int = 0, graphs: bool = False):
+                 light_blocks: int = 0, graphs: bool = False, users_only: bool = False):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -50,7 +52,7 @@ class CoreALS:
         p.budget_num, p.budget_den = int(budget[0]), int(budget[1])
         p.min_keep = int(min_keep)
         p.precision = int(precision)
-        p.flags = capi.ALS_VALIDATE if validate else 0
+        p.flags = (capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
         p.stream = self.stream.cuda_stream
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)
@@ -131,3 +133,107 @@ def run_als(als: CoreALS, M0: torch.Tensor, iters: int, record: bool = False):
         if record:
             hist.append(als.objective(U, M))
     return U, M, hist
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class FoldIn:
+    """Fold-in network 64 -> hidden -> hidden -> 64 (GELU) over the rating-weighted
+    embedding bag of item factors, with FP32 master weights in a device workspace."""
+
+    def __init__(self, n_f: int, params: torch.Tensor, hidden: int = 256, max_batch: int = 4096,
+                 precision: int = capi.FOLDIN_BF16, max_train_rows: int = 0, lr: float = 1e-3,
+                 betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 0.0, stream=None):
+        capi.load()
+        self.n_f, self.hidden = int(n_f), int(hidden)
+        self.P = capi.foldin_param_count(self.n_f, self.hidden)
+        _need(params, torch.float32, self.P, "params")
+        self.device = params.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cfg = capi.foldin_cfg()
+        cfg.n_f, cfg.hidden, cfg.max_batch, cfg.precision = self.n_f, self.hidden, int(max_batch), int(precision)
+        cfg.max_train_rows = int(max_train_rows)
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay = lr, betas[0], betas[1], eps, weight_decay
+        cfg.stream = self.stream.cuda_stream
+        size = capi.foldin_workspace_size(cfg)
+        if size == 0:
+            raise capi.ALSError(capi.ALS_E_ARG, "invalid fold-in configuration")
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        cfg.workspace, cfg.workspace_bytes = self.workspace.data_ptr(), size
+        self.cfg = cfg
+        self.max_batch = int(max_batch)
+        self.m = capi.foldin_create(cfg, params.data_ptr())
+
+    @staticmethod
+    def _csr(ptr, items, vals):
+        _need(ptr, torch.int64, None, "ptr")
+        _need(items, torch.int32, None, "items")
+        _need(vals, torch.float32, items.numel(), "vals")
+        return ptr.data_ptr(), items.data_ptr(), vals.data_ptr()
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        capi.foldin_get_params(self.m, out.data_ptr())
+        return out
+
+    def set_params(self, params: torch.Tensor) -> None:
+        _need(params, torch.float32, self.P, "params")
+        capi.foldin_set_params(self.m, params.data_ptr())
+
+    def forward(self, M, ptr, items, vals, rows: Optional[torch.Tensor] = None, n: Optional[int] = None):
+        n = int(rows.numel()) if rows is not None else (int(n) if n is not None else ptr.numel() - 1)
+        if rows is not None:
+            _need(rows, torch.int32, n, "rows")
+        _need(M, torch.float32, None, "M")
+        out = torch.empty(n, self.n_f, dtype=torch.float32, device=self.device)
+        capi.foldin_forward(self.m, M.data_ptr(), *self._csr(ptr, items, vals), _ptr(rows), n, out.data_ptr())
+        return out
+
+    def grad(self, M, ptr, items, vals, target, rows: Optional[torch.Tensor] = None, n: Optional[int] = None):
+        """Gradient (device [P]) and loss (device [1]) of one batch."""
+        n = int(rows.numel()) if rows is not None else int(n)
+        if rows is not None:
+            _need(rows, torch.int32, n, "rows")
+        _need(M, torch.float32, None, "M")
+        _need(target, torch.float32, None, "target")
+        g = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        capi.foldin_grad(self.m, M.data_ptr(), *self._csr(ptr, items, vals), _ptr(rows), n, target.data_ptr(),
+                         g.data_ptr(), loss.data_ptr())
+        return g, loss
+
+    def adamw(self, grad: Optional[torch.Tensor] = None) -> None:
+        if grad is not None:
+            _need(grad, torch.float32, self.P, "grad")
+        capi.foldin_adamw(self.m, _ptr(grad))
+
+    def train(self, M, ptr, items, vals, target, epochs: int, batch: int, seed: int = 0):
+        n_rows = ptr.numel() - 1
+        _need(M, torch.float32, None, "M")
+        _need(target, torch.float32, n_rows * self.n_f, "target")
+        return capi.foldin_train(self.m, M.data_ptr(), *self._csr(ptr, items, vals), n_rows, target.data_ptr(),
+                                 int(epochs), int(batch), int(seed))
+
+    def answer(self, query: CoreALS, M: torch.Tensor, tol: float = 1e-3, stats: bool = True):
+        """(U_new, path, rho, stats) for the users of the query context."""
+        _need(M, torch.float32, query.n_m * self.n_f, "M")
+        n = query.n_u
+        U = torch.empty(n, self.n_f, dtype=torch.float32, device=self.device)
+        path = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        rho = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
+        st = capi.foldin_answer(query.ctx, self.m, M.data_ptr(), tol, U.data_ptr(), path.data_ptr(),
+                                rho.data_ptr(), stats)
+        return U, path[:n], rho[:n], st
+
+    def close(self) -> None:
+        if getattr(self, "m", None):
+            capi.foldin_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcoreals.so")
-SOURCES = ["capi.hip", "setup.hip", "sweep.hip", "heavy.hip", "objective.hip"]
+SOURCES = ["capi.hip", "setup.hip", "sweep.hip", "heavy.hip", "objective.hip", "foldin.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

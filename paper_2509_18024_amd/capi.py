@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libcoreals.so")
 ALS_OK, ALS_E_ARG, ALS_E_INDEX, ALS_E_VALUE, ALS_E_NOMEM, ALS_E_DEVICE, ALS_E_STATE = range(7)
 ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES, ALS_PREC_AUTO = 0, 1, 2, 3
 ALS_VALIDATE = 1
+ALS_USERS_ONLY = 2
+FOLDIN_BF16, FOLDIN_FP32 = 0, 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
                 5: "ALS_E_DEVICE", 6: "ALS_E_STATE"}
@@ -46,6 +48,21 @@ class als_objective(ctypes.Structure):
                 ("remse", ctypes.c_double)]
 
 
+class foldin_cfg(ctypes.Structure):
+    _fields_ = [
+        ("n_f", ctypes.c_int32), ("hidden", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("max_train_rows", ctypes.c_int64),
+        ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float),
+        ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class foldin_answer_stats(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_mlp", ctypes.c_int64), ("n_exact", ctypes.c_int64),
+                ("n_empty", ctypes.c_int64), ("n_singular_fallback", ctypes.c_int64)]
+
+
 class ALSError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -56,7 +73,10 @@ _lib = None
 
 EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_items",
            "core_select_count", "core_select", "objective", "als_profile_begin", "als_profile_end",
-           "als_class_counts", "als_use_graphs", "als_destroy", "als_last_error"]
+           "als_class_counts", "als_use_graphs", "als_destroy", "als_last_error",
+           "foldin_param_count", "foldin_workspace_size", "foldin_create", "foldin_get_params",
+           "foldin_set_params", "foldin_forward", "foldin_grad", "foldin_adamw", "foldin_train",
+           "foldin_answer", "foldin_destroy", "foldin_last_error"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
 NPROF = 12
@@ -100,6 +120,29 @@ def load():
     L.als_destroy.argtypes = [vp]
     L.als_last_error.restype = ctypes.c_char_p
     L.als_last_error.argtypes = [vp]
+    L.foldin_param_count.restype = i64
+    L.foldin_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.foldin_workspace_size.restype = ctypes.c_size_t
+    L.foldin_workspace_size.argtypes = [ctypes.POINTER(foldin_cfg)]
+    L.foldin_create.restype = i32
+    L.foldin_create.argtypes = [ctypes.POINTER(foldin_cfg), vp, ctypes.POINTER(vp)]
+    for name in ("foldin_get_params", "foldin_set_params", "foldin_adamw"):
+        f = getattr(L, name)
+        f.restype = i32
+        f.argtypes = [vp, vp]
+    L.foldin_forward.restype = i32
+    L.foldin_forward.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+    L.foldin_grad.restype = i32
+    L.foldin_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+    L.foldin_train.restype = i32
+    L.foldin_train.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                               ctypes.POINTER(ctypes.c_float)]
+    L.foldin_answer.restype = i32
+    L.foldin_answer.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(foldin_answer_stats)]
+    L.foldin_destroy.restype = None
+    L.foldin_destroy.argtypes = [vp]
+    L.foldin_last_error.restype = ctypes.c_char_p
+    L.foldin_last_error.argtypes = [vp]
     _lib = L
     return L
 
@@ -179,3 +222,64 @@ def als_destroy(ctx) -> None:
 def als_last_error(ctx) -> str:
     m = load().als_last_error(ctx)
     return m.decode() if m else ""
+
+
+# ---------------------------------------------------------------- fold-in
+
+def _fcheck(status: int, model) -> None:
+    if status != ALS_OK:
+        msg = load().foldin_last_error(model) if model else b"invalid configuration or workspace"
+        raise ALSError(status, msg.decode() if msg else "")
+
+
+def foldin_param_count(n_f: int, hidden: int) -> int:
+    return int(load().foldin_param_count(n_f, hidden))
+
+
+def foldin_workspace_size(cfg: foldin_cfg) -> int:
+    return int(load().foldin_workspace_size(ctypes.byref(cfg)))
+
+
+def foldin_create(cfg: foldin_cfg, params_ptr: int):
+    m = ctypes.c_void_p()
+    _fcheck(load().foldin_create(ctypes.byref(cfg), params_ptr, ctypes.byref(m)), None)
+    return m
+
+
+def foldin_get_params(m, params_ptr: int) -> None:
+    _fcheck(load().foldin_get_params(m, params_ptr), m)
+
+
+def foldin_set_params(m, params_ptr: int) -> None:
+    _fcheck(load().foldin_set_params(m, params_ptr), m)
+
+
+def foldin_forward(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, rows_ptr, n, out_ptr) -> None:
+    _fcheck(load().foldin_forward(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, rows_ptr, n, out_ptr), m)
+
+
+def foldin_grad(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, rows_ptr, n, target_ptr, grad_ptr, loss_ptr) -> None:
+    _fcheck(load().foldin_grad(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, rows_ptr, n, target_ptr, grad_ptr,
+                               loss_ptr), m)
+
+
+def foldin_adamw(m, grad_ptr) -> None:
+    _fcheck(load().foldin_adamw(m, grad_ptr), m)
+
+
+def foldin_train(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, n_rows, target_ptr, epochs, batch, seed):
+    losses = (ctypes.c_float * max(epochs, 1))()
+    _fcheck(load().foldin_train(m, M_ptr, ptr_ptr, items_ptr, vals_ptr, n_rows, target_ptr, epochs, batch,
+                                seed, losses), m)
+    return list(losses[:epochs])
+
+
+def foldin_answer(ctx, m, M_ptr, tol, U_ptr, path_ptr, rho_ptr, stats: bool = False):
+    st = foldin_answer_stats() if stats else None
+    _fcheck(load().foldin_answer(ctx, m, M_ptr, float(tol), U_ptr, path_ptr, rho_ptr,
+                                 ctypes.byref(st) if st else None), m)
+    return st
+
+
+def foldin_destroy(m) -> None:
+    load().foldin_destroy(m)

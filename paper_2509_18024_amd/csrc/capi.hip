@@ -81,11 +81,13 @@ int64_t pair_bound(const als_problem &p, int64_t n_rows) {
 Layout carve(const als_problem &p, void *base) {
     Carve c{reinterpret_cast<char *>(base), 0, 0};
     Layout L;
-    L.col_ptr = c.take<int64_t>((size_t)p.n_m + 1);
-    L.row_idx = c.take<int32_t>((size_t)p.nnz);
-    L.val_t = c.take<float>((size_t)p.nnz);
+    // ALS_USERS_ONLY: no column view and no items-side schedule
+    const bool uo = (p.flags & ALS_USERS_ONLY) != 0;
+    L.col_ptr = c.take<int64_t>(uo ? 1 : (size_t)p.n_m + 1);
+    L.row_idx = c.take<int32_t>(uo ? 0 : (size_t)p.nnz);
+    L.val_t = c.take<float>(uo ? 0 : (size_t)p.nnz);
     L.perm_u = c.take<int32_t>((size_t)p.n_u);
-    L.perm_m = c.take<int32_t>((size_t)p.n_m);
+    L.perm_m = c.take<int32_t>(uo ? 0 : (size_t)p.n_m);
     L.stats = c.take<unsigned long long>(NSTATS);
     L.queues = c.take<unsigned int>(2 * 16);
     L.class_count = c.take<int64_t>(2 * NCLASS);
@@ -94,18 +96,18 @@ Layout carve(const als_problem &p, void *base) {
     L.obj_partials = c.take<double>((size_t)5 * objective_blocks());
     L.obj_out = c.take<double>(4);
     L.partials = c.take<float>((size_t)pair_cap_of(p) * (NF + 1) * 64);
-    L.resid = c.take<double>((size_t)pair_cap_of(p) * 64);
+    L.resid = c.take<double>((size_t)pair_cap_of(p) * 128);
     for (int sd = 0; sd < 2; ++sd) {
-        const int64_t nr = sd == 0 ? p.n_u : p.n_m;
-        const int64_t hb = heavy_bound(p, nr), pb = pair_bound(p, nr);
+        const int64_t nr = sd == 0 ? p.n_u : (uo ? 0 : p.n_m);
+        const int64_t hb = heavy_bound(p, nr), pb = nr ? pair_bound(p, nr) : 0;
         L.side[sd].pair_slot = c.take<int32_t>((size_t)pb);
         L.side[sd].pair_chunk = c.take<int32_t>((size_t)pb);
         L.side[sd].pair_off = c.take<int64_t>((size_t)hb + 1);
         L.side[sd].cutT = c.take<int32_t>((size_t)hb * 64);
         L.side[sd].cutK = c.take<int32_t>((size_t)hb * 64);
     }
-    size_t tb = csc_temp_bytes(p.nnz, p.n_m);
-    size_t tp = perm_temp_bytes(p.n_u > p.n_m ? p.n_u : p.n_m);
+    size_t tb = uo ? 0 : csc_temp_bytes(p.nnz, p.n_m);
+    size_t tp = perm_temp_bytes(uo ? p.n_u : std::max(p.n_u, p.n_m));
     L.temp_bytes = tb > tp ? tb : tp;
     L.temp = c.take<char>(L.temp_bytes);
     L.total = c.off;
@@ -135,7 +137,9 @@ als_status fail(als_ctx *c, als_status st, const char *fmt, const char *detail =
     } while (0)
 
 // All launches of one half-sweep, in stream order (also what a graph captures).
-als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *out) {
+// chk (fold-in answers, users side): keep each row's candidate when its
+// relative residual passes, solve the others exactly.
+als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *out, const CheckArgs *chk) {
     const Side &S = c->side[side];
     unsigned int *queues = c->queues + side * 16;
     // counters are cleared by a kernel, not a memset node, so that replays of a
@@ -158,7 +162,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         return e;
     };
     for (int cls = 0; cls < CLS_HEAVY; ++cls) {
-        SweepArgs a;
+        SweepArgs a{};
         a.ptr = S.ptr;
         a.idx = S.idx;
         a.val = S.val;
@@ -173,15 +177,20 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         a.min_keep = c->p.min_keep;
         a.stats = c->stats;
         a.queue = queues + cls;
+        a.guess = chk ? chk->guess : nullptr;
+        a.tol = chk ? chk->tol : 0.f;
+        a.path = chk ? chk->path : nullptr;
+        a.rho = chk ? chk->rho : nullptr;
         if (a.count <= 0) continue;
         als_ctx::Mark mk{};
         HIP_CHECK(c, mark_begin(cls, mk));
-        HIP_CHECK(c, launch_sweep_class(cls, a, c->light_blocks, c->stream));
+        if (chk) HIP_CHECK(c, launch_check_class(cls, a, c->light_blocks, c->stream));
+        else HIP_CHECK(c, launch_sweep_class(cls, a, c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(mk));
     }
     const HeavyPlan &H = S.heavy;
     if (H.n_heavy > 0) {
-        HeavyArgs h;
+        HeavyArgs h{};
         h.ptr = S.ptr;
         h.idx = S.idx;
         h.val = S.val;
@@ -207,6 +216,10 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.fp64res = c->fp64res ? 1 : 0;
         h.stats = c->stats;
         h.queue = queues + CLS_HEAVY;
+        h.guess = nullptr;
+        h.tol = 0.f;
+        h.path = nullptr;
+        h.rho = nullptr;
         if (c->p.budget_num < c->p.budget_den) {
             als_ctx::Mark mk{};
             HIP_CHECK(c, mark_begin(PROF_HSELECT, mk));
@@ -214,6 +227,17 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
             HIP_CHECK(c, mark_end(mk));
         }
         for (const auto &b : H.batches) {
+            if (chk) {
+                // candidate residuals of the batch's rows; accepted rows are then
+                // skipped by every kernel below (path 0)
+                h.guess = chk->guess;
+                h.tol = chk->tol;
+                h.path = nullptr;
+                h.rho = chk->rho;
+                HIP_CHECK(c, launch_heavy_check(h, b.pair_begin, b.pair_end, c->stream));
+                h.path = chk->path;
+                HIP_CHECK(c, launch_heavy_check_reduce(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+            }
             als_ctx::Mark mg{}, ms{};
             HIP_CHECK(c, mark_begin(PROF_HGRAM, mg));
             if (c->bf16) HIP_CHECK(c, launch_heavy_gram_bf16(h, b.pair_begin, b.pair_end, c->stream));
@@ -241,6 +265,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
 
 als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st) {
     if (!c) return ALS_E_STATE;
+    if (side == 1 && c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
     if (!other || !out) return fail(c, ALS_E_ARG, "NULL factor pointer%s");
     if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
     if (c->use_graphs && !c->profiling) {
@@ -252,7 +277,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
             }
             hipGraph_t g = nullptr;
             HIP_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            als_status rs = enqueue_half_sweep(c, side, other, out);
+            als_status rs = enqueue_half_sweep(c, side, other, out, nullptr);
             hipError_t ec = hipStreamEndCapture(c->stream, &g);
             if (rs != ALS_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -267,7 +292,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         }
         HIP_CHECK(c, hipGraphLaunch(G.exec, c->stream));
     } else {
-        als_status rs = enqueue_half_sweep(c, side, other, out);
+        als_status rs = enqueue_half_sweep(c, side, other, out, nullptr);
         if (rs != ALS_OK) return rs;
     }
     if (st) {
@@ -283,6 +308,24 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
 }
 
 }  // namespace
+
+namespace coreals {
+
+als_status enqueue_checked_users(als_ctx *c, const float *M, float *out, const CheckArgs &chk) {
+    if (!c) return ALS_E_STATE;
+    HIP_CHECK(c, launch_zero_u64(c->stats, NSTATS, c->stream));
+    return enqueue_half_sweep(c, 0, M, out, &chk);
+}
+
+als_status read_stats(als_ctx *c, unsigned long long *h) {
+    HIP_CHECK(c, hipMemcpyAsync(h, c->stats, sizeof(unsigned long long) * NSTATS, hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(c, hipStreamSynchronize(c->stream));
+    return ALS_OK;
+}
+
+als_status set_error(als_ctx *c, als_status st, const char *msg) { return fail(c, st, "%s", msg); }
+
+}  // namespace coreals
 
 extern "C" {
 
@@ -329,6 +372,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->pair_cap = pair_cap_of(*p);
     c->temp = L.temp;
     c->temp_bytes = L.temp_bytes;
+    c->users_only = (p->flags & ALS_USERS_ONLY) != 0;
+    const int n_sides = c->users_only ? 1 : 2;
 
     auto bail = [&](als_status st, const std::string &msg) {
         g_init_error = msg;
@@ -354,8 +399,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (flags & 4) return bail(ALS_E_VALUE, "NaN or Inf among the ratings");
 
     // 2. column view
-    INIT_HIP(build_csc(p->n_u, p->n_m, p->nnz, p->row_ptr, p->col_idx, p->val, L.col_ptr, L.row_idx, L.val_t,
-                       L.temp, s));
+    if (!c->users_only)
+        INIT_HIP(build_csc(p->n_u, p->n_m, p->nnz, p->row_ptr, p->col_idx, p->val, L.col_ptr, L.row_idx, L.val_t,
+                           L.temp, s));
 
     // 3. schedules
     Side &U = c->side[0];
@@ -366,15 +412,17 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     U.val = p->val;
     U.perm = L.perm_u;
     Side &M = c->side[1];
-    M.n_rows = p->n_m;
+    M.n_rows = c->users_only ? 0 : p->n_m;
     M.n_other = p->n_u;
     M.ptr = L.col_ptr;
     M.idx = L.row_idx;
     M.val = L.val_t;
     M.perm = L.perm_m;
-    int64_t host_counts[2 * NCLASS];
-    int64_t host_max[2];
-    for (int sd = 0; sd < 2; ++sd) {
+    int64_t host_counts[2 * NCLASS] = {};
+    int64_t host_max[2] = {};
+    INIT_HIP(hipMemsetAsync(L.class_count, 0, sizeof(int64_t) * 2 * NCLASS, s));
+    INIT_HIP(hipMemsetAsync(L.max_deg, 0, sizeof(int64_t) * 2, s));
+    for (int sd = 0; sd < n_sides; ++sd) {
         Side &S = c->side[sd];
         INIT_HIP(build_schedule(S.n_rows, S.ptr, p->budget_num, p->budget_den, p->min_keep, c->heavy_n, S.perm,
                                 L.class_count + sd * NCLASS, L.max_deg + sd, L.temp, s));
@@ -389,7 +437,7 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         S.max_deg = host_max[sd];
     }
     // heavy-row plan: chunk pairs and batches that fit the partial scratch
-    for (int sd = 0; sd < 2; ++sd) {
+    for (int sd = 0; sd < n_sides; ++sd) {
         Side &S = c->side[sd];
         HeavyPlan &H = S.heavy;
         H.n_heavy = S.class_off[CLS_HEAVY + 1] - S.class_off[CLS_HEAVY];
@@ -452,6 +500,7 @@ als_status half_sweep_items(als_ctx *c, const float *U, float *M, als_sweep_stat
 als_status core_select_count(als_ctx *c, int side, int64_t row_begin, int64_t row_end, int64_t *count) {
     if (!c) return ALS_E_STATE;
     if (side != 0 && side != 1) return fail(c, ALS_E_ARG, "side must be 0 or 1%s");
+    if (side == 1 && c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
     if (!count) return fail(c, ALS_E_ARG, "count is NULL%s");
     const Side &S = c->side[side];
     if (row_begin < 0 || row_end < row_begin || row_end > S.n_rows) return fail(c, ALS_E_ARG, "bad row range%s");
@@ -469,6 +518,7 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
                        int64_t *sel_ptr, int32_t *sel_pos, int64_t sel_cap) {
     if (!c) return ALS_E_STATE;
     if (side != 0 && side != 1) return fail(c, ALS_E_ARG, "side must be 0 or 1%s");
+    if (side == 1 && c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
     if (!other || !sel_ptr || (!sel_pos && sel_cap > 0)) return fail(c, ALS_E_ARG, "NULL pointer%s");
     const Side &S = c->side[side];
     if (row_begin < 0 || row_end < row_begin || row_end > S.n_rows) return fail(c, ALS_E_ARG, "bad row range%s");
@@ -522,6 +572,7 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
 
 als_status objective(als_ctx *c, const float *U, const float *M, als_objective *out) {
     if (!c) return ALS_E_STATE;
+    if (c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
     if (!U || !M || !out) return fail(c, ALS_E_ARG, "NULL pointer%s");
     HIP_CHECK(c, launch_objective(c->p.n_u, c->p.n_m, c->p.n_f, c->p.row_ptr, c->p.col_idx, c->p.val, c->col_ptr, U,
                                   M, c->p.lambda, c->obj_partials, c->obj_out, c->stream));

@@ -25,6 +25,10 @@
 // X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
 // second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the same
 // (re-factored) matrix and returns u + d.
+//
+// Fold-in answers (check mode) add k_heavy_check / k_heavy_check_reduce,
+// the relative residual of a candidate answer from per-chunk shares, before
+// the Gram; rows whose candidate passes are skipped by the later kernels.
 #include <type_traits>
 
 #include "rowops.hpp"
@@ -301,6 +305,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram(HeavyArgs a, int64_t pa
         const int64_t slot = a.pair_slot[p];
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -332,6 +337,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
          slot += (int64_t)gridDim.x * WPB) {
         const int lane = opaque_lane(lane0);
         const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -402,6 +408,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
         const int64_t slot = a.pair_slot[p];
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -484,6 +491,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t p
         const int64_t slot = a.pair_slot[p];
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -525,6 +533,69 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t p
     }
 }
 
+// Fold-in check, part 1: per (row, chunk) pair, the chunk's share of
+// b_a = sum over kept k of x_ka y_k and of X*^T (y - X g) for the candidate g
+// (FP64 sums), into resid[pair][0..63] and resid[pair][64..127].
+__global__ __launch_bounds__(WPB * 64) void k_heavy_check(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    __shared__ WaveLds lds[WPB];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    WaveLds &L = lds[w];
+    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
+        const int64_t slot = a.pair_slot[p];
+        const int chunk = a.pair_chunk[p];
+        const int64_t i = a.rows[slot];
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+        Cut c;
+        if (s == n) c = Cut{0, 0, false, true};
+        else if (s == 0) c = Cut{0, 0, true, false};
+        else c = Cut{a.cutT[slot * 64 + lane], a.cutK[slot * 64 + lane], false, false};
+        wave_sync();
+        L.urhs[lane] = lane < a.nf ? a.guess[i * a.nf + lane] : 0.f;
+        wave_sync();
+        const int kb = chunk * a.chunk;
+        const int ke = min(n, kb + a.chunk);
+        double rho, bsum;
+        resid_range(L, r, c, kb, ke, lane, rho, bsum);
+        double *dst = a.resid + (p - pair_begin) * 128;
+        dst[lane] = rho;
+        dst[64 + lane] = bsum;
+    }
+}
+
+// Fold-in check, part 2: one wavefront per heavy row sums its chunk shares in
+// chunk order, subtracts lambda n_i g, and accepts g (path 0, copied to out)
+// when |b - A g| / |b| <= tol; otherwise marks the row for the exact solve.
+__global__ __launch_bounds__(WPB * 64) void k_heavy_check_reduce(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
+                                                                 int64_t pair_base) {
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int64_t slot = slot_begin + (int64_t)blockIdx.x * WPB + w; slot < slot_end;
+         slot += (int64_t)gridDim.x * WPB) {
+        const int64_t i = a.rows[slot];
+        const int n = (int)(a.ptr[i + 1] - a.ptr[i]);
+        double rho = 0.0, bsum = 0.0;
+        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p) {
+            rho += a.resid[(p - pair_base) * 128 + lane];
+            bsum += a.resid[(p - pair_base) * 128 + 64 + lane];
+        }
+        const float g = lane < a.nf ? a.guess[i * a.nf + lane] : 0.f;
+        rho -= (double)a.lam * (double)n * (double)g;
+        const double rel = rel_residual(rho, bsum, lane, a.nf);
+        const bool accept = rel <= (double)a.tol;
+        if (lane == 0) {
+            a.rho[i] = (float)rel;
+            a.path[i] = accept ? 0 : 1;
+            if (!accept) atomicAdd(&a.stats[ST_FOLDIN_EXACT], 1ull);
+        }
+        if (accept && lane < a.nf) a.out[i * a.nf + lane] = g;
+    }
+}
+
 unsigned blocks_for(int64_t items, int per_block, int64_t cap) {
     int64_t b = (items + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -549,6 +620,23 @@ hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pa
     else
         hipLaunchKernelGGL(k_heavy_resid<false>, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64),
                            0, s, a, pair_begin, pair_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_check(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
+    if (pair_end <= pair_begin) return hipSuccess;
+    if (!a.guess) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_heavy_check, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
+                       pair_begin, pair_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_check_reduce(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
+                                     hipStream_t s) {
+    if (slot_end <= slot_begin) return hipSuccess;
+    if (!a.guess || !a.path || !a.rho) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_heavy_check_reduce, dim3(blocks_for(slot_end - slot_begin, WPB, 65536)), dim3(WPB * 64), 0,
+                       s, a, slot_begin, slot_end, pair_base);
     return hipGetLastError();
 }
 

@@ -100,7 +100,7 @@ struct Side {
 constexpr int NPROF = 12;
 enum ProfSlot : int { PROF_HSELECT = 7, PROF_HGRAM = 8, PROF_HSOLVE = 9, PROF_HRESID = 10, PROF_HREFINE = 11 };
 
-enum StatSlot : int { ST_EMPTY = 0, ST_FALLBACK = 1, ST_FP64RES = 2, ST_ROWS = 3, NSTATS = 8 };
+enum StatSlot : int { ST_EMPTY = 0, ST_FALLBACK = 1, ST_FP64RES = 2, ST_ROWS = 3, ST_FOLDIN_EXACT = 4, NSTATS = 8 };
 
 struct SweepArgs {
     const int64_t *ptr;
@@ -116,6 +116,12 @@ struct SweepArgs {
     int32_t min_keep;
     unsigned long long *stats;
     unsigned int *queue;     // row counter of this class (persistent launch)
+    // fold-in check mode: candidate answers, acceptance threshold on the
+    // relative residual, per-row outcome (0 candidate kept, 1 solved) and residual
+    const float *guess;
+    float tol;
+    int32_t *path;
+    float *rho;
 };
 
 struct HeavyArgs {
@@ -138,11 +144,17 @@ struct HeavyArgs {
     int32_t *cutT;
     int32_t *cutK;
     float *partials;
-    double *resid;            // [pair_cap * 64] refinement residual partials
+    double *resid;            // [pair_cap * 128] refinement / check residual partials
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
     int32_t fp64res;          // residual accumulated in FP64
     unsigned long long *stats;
     unsigned int *queue;      // heavy-row selection counter (nullptr: grid-stride)
+    // fold-in check mode (see SweepArgs); with path set, the Gram, solve and
+    // refinement kernels skip rows whose candidate was accepted (path 0)
+    const float *guess;
+    float tol;
+    int32_t *path;
+    float *rho;
 };
 
 struct SelectArgs {
@@ -160,9 +172,18 @@ struct SelectArgs {
     const int32_t *cutK;
 };
 
+// Fold-in check mode of a users half-sweep (see SweepArgs).
+struct CheckArgs {
+    const float *guess;
+    float tol;
+    int32_t *path;
+    float *rho;
+};
+
 // launchers (sweep.hip)
 hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_check_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s);
 
 // launchers (heavy.hip)
 hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s);
@@ -171,6 +192,9 @@ hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t sl
                               hipStream_t s);
 hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
+hipError_t launch_heavy_check(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
+hipError_t launch_heavy_check_reduce(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
+                                     hipStream_t s);
 
 // launchers (setup.hip)
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
@@ -209,7 +233,7 @@ struct als_ctx {
     double *obj_partials = nullptr;
     double *obj_out = nullptr;            // [4]
     float *partials = nullptr;            // [pair_cap * (NF + 1) * 64]
-    double *resid = nullptr;              // [pair_cap * 64]
+    double *resid = nullptr;              // [pair_cap * 128]
     int32_t heavy_n = coreals::DEFAULT_HEAVY_N;
     int32_t chunk = coreals::DEFAULT_CHUNK;
     int64_t pair_cap = coreals::PAIR_CAP;
@@ -235,4 +259,17 @@ struct als_ctx {
     bool use_graphs = false;
     Graph graph[2];
     unsigned int *queues = nullptr;  // [2 * 16] row counters
+    bool users_only = false;         // ALS_USERS_ONLY: no column view, users side only
 };
+
+namespace coreals {
+
+// Users half-sweep of c in fold-in check mode (stats cleared first); used by
+// the fold-in entry points.
+als_status enqueue_checked_users(als_ctx *c, const float *M, float *out, const CheckArgs &chk);
+// Copy the per-row event counters to the host (syncs the context's stream).
+als_status read_stats(als_ctx *c, unsigned long long *h);
+// Record an error message on c and return st.
+als_status set_error(als_ctx *c, als_status st, const char *msg);
+
+}  // namespace coreals

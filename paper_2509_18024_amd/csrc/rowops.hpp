@@ -208,6 +208,59 @@ __device__ __forceinline__ void gram_range(WaveLds &L, RowCtx &r, const Cut &c, 
     }
 }
 
+// Matrix-free residual of a candidate solution g of the row's system, with
+// g_a parked in L.urhs[a]: over positions [kb, ke), lane a accumulates
+// rho_a = sum over kept k of x_ka (y_k - x_k . g) and b_a = sum over kept k of
+// x_ka y_k (the right-hand side of eq. core_ui).  Products in FP32, sums in FP64.
+__device__ __forceinline__ void resid_range(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+                                            double &rho, double &bsum) {
+    rho = 0.0;
+    bsum = 0.0;
+    if (c.none) return;
+    for (int k0 = kb; k0 < ke; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, ke - k0);
+        float rk = 0.f;
+        if (lane < m) {
+            float dot = 0.f;
+#pragma unroll
+            for (int b4 = 0; b4 < NF / 4; ++b4) {
+                const float4 xr = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
+                dot = fmaf(xr.x, L.urhs[4 * b4 + 0], dot);
+                dot = fmaf(xr.y, L.urhs[4 * b4 + 1], dot);
+                dot = fmaf(xr.z, L.urhs[4 * b4 + 2], dot);
+                dot = fmaf(xr.w, L.urhs[4 * b4 + 3], dot);
+            }
+            rk = L.y[lane] - dot;
+        }
+        L.rres[lane] = (double)rk;
+        wave_sync();
+        for (int k = 0; k < m; ++k) {
+            const float x = L.X[k][lane];
+            if (kept(c, key_of(x), k0 + k)) {
+                rho += (double)x * L.rres[k];
+                bsum += (double)x * (double)L.y[k];
+            }
+        }
+        wave_sync();
+    }
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Relative residual |b - A g| / |b| from the lanes' rho_a (already minus
+// lambda n g_a) and b_a; +inf when b = 0 (no answer is accepted then).
+__device__ __forceinline__ double rel_residual(double rho, double bsum, int lane, int nf) {
+    if (lane >= nf) rho = bsum = 0.0;
+    const double rr = wave_sum_d(rho * rho);
+    const double bb = wave_sum_d(bsum * bsum);
+    return bb > 0.0 ? sqrt(rr / bb) : __builtin_inf();
+}
+
 __device__ __forceinline__ void gram(WaveLds &L, RowCtx &r, const Cut &c, int lane, float (&A)[NF], float &rhs) {
     gram_range(L, r, c, 0, r.n, lane, A, rhs);
 }

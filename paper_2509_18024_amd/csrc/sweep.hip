@@ -11,6 +11,11 @@
 //   4. solve:  pivoted LU in registers, or LDL^T when s == n (eq. (U)).  A
 //              pivot below n_f 2^-23 max|A| sends a core row to the full-data
 //              update.
+//
+// The check variant (fold-in answers) inserts between 2 and 3 the relative
+// residual |b - A g| / |b| of a candidate g, formed matrix-free from the
+// staged rows (b - A g = X*^T (y - X g) - lambda n_i g), and skips 3 and 4
+// when it is within the tolerance.
 #include "rowops.hpp"
 
 namespace coreals {
@@ -27,7 +32,10 @@ __device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, in
     else return select_net<32>(L, r, s, lane);
 }
 
-template <int CLS>
+// CHECK (fold-in answers): the row's candidate solution a.guess[i] is kept when
+// the relative residual of the row's system (the one the sweep would solve)
+// is at most a.tol; otherwise the row is solved exactly as in the sweep.
+template <int CLS, bool CHECK>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     __shared__ WaveLds lds[WPB];
     const int w = threadIdx.x >> 6;
@@ -49,16 +57,45 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
         RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
         if (n == 0) {
             if (lane < a.nf) a.out[i * a.nf + lane] = 0.f;
-            if (lane == 0) atomicAdd(&a.stats[ST_EMPTY], 1ull);
+            if (lane == 0) {
+                atomicAdd(&a.stats[ST_EMPTY], 1ull);
+                if constexpr (CHECK) {
+                    a.path[i] = 1;
+                    a.rho[i] = __builtin_inff();
+                }
+            }
             continue;
         }
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
         const float lamn = (float)((double)a.lam * (double)n);
         constexpr bool kCore = CLS != CLS_FULL;
+        float g = 0.f;
+        if constexpr (CHECK) {
+            g = lane < a.nf ? a.guess[i * a.nf + lane] : 0.f;
+            wave_sync();
+            L.urhs[lane] = g;
+            wave_sync();
+        }
         Cut c{0, 0, false, true};
         if constexpr (kCore) {
             if (s == 0) c = Cut{0, 0, true, false};
             else c = select_for_class<CLS>(L, r, s, lane);
+        }
+        if constexpr (CHECK) {
+            double rho, bsum;
+            resid_range(L, r, c, 0, n, lane, rho, bsum);
+            rho -= (double)a.lam * (double)n * (double)g;
+            const double rel = rel_residual(rho, bsum, lane, a.nf);
+            const bool accept = rel <= (double)a.tol;  // false for NaN
+            if (lane == 0) {
+                a.rho[i] = (float)rel;
+                a.path[i] = accept ? 0 : 1;
+                if (!accept) atomicAdd(&a.stats[ST_FOLDIN_EXACT], 1ull);
+            }
+            if (accept) {
+                if (lane < a.nf) a.out[i * a.nf + lane] = g;
+                continue;
+            }
         }
         float A[NF];
         float rhs;
@@ -81,13 +118,21 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
 }
 
 // Full-data light rows (LDL^T, no pivot search): fits two waves per SIMD as is.
-__global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL>(a); }
+__global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL, false>(a); }
 
 // Core light rows: the pivot search raises register demand; capping the
 // kernel at two waves per SIMD (a few spills) beats one wave per SIMD.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
-    sweep_rows<CLS>(a);
+    sweep_rows<CLS, false>(a);
+}
+
+// Fold-in answers: residual check of the candidates, exact solve of the rest.
+__global__ __launch_bounds__(WPB * 64) void k_check_full(SweepArgs a) { sweep_rows<CLS_FULL, true>(a); }
+
+template <int CLS>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_check_core(SweepArgs a) {
+    sweep_rows<CLS, true>(a);
 }
 
 // CES positions for a contiguous row range (the core_select entry point).
@@ -137,32 +182,49 @@ __global__ __launch_bounds__(WPB * 64) void k_select(SelectArgs a) {
     }
 }
 
-template <int CLS>
+template <int CLS, bool CHECK>
 hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
     int64_t blocks = (a.count + WPB - 1) / WPB;
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     if (blocks > 256 * 64) blocks = 256 * 64;
-    if constexpr (CLS == CLS_FULL)
-        hipLaunchKernelGGL(k_sweep_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    if constexpr (CHECK) {
+        if constexpr (CLS == CLS_FULL)
+            hipLaunchKernelGGL(k_check_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_check_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    } else {
+        if constexpr (CLS == CLS_FULL)
+            hipLaunchKernelGGL(k_sweep_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    }
     return hipGetLastError();
+}
+
+template <bool CHECK>
+hipError_t launch_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    switch (cls) {
+        case CLS_FULL: return launch_one<CLS_FULL, CHECK>(a, max_blocks, s);
+        case CLS_NET1: return launch_one<CLS_NET1, CHECK>(a, max_blocks, s);
+        case CLS_NET2: return launch_one<CLS_NET2, CHECK>(a, max_blocks, s);
+        case CLS_NET4: return launch_one<CLS_NET4, CHECK>(a, max_blocks, s);
+        case CLS_NET8: return launch_one<CLS_NET8, CHECK>(a, max_blocks, s);
+        case CLS_NET16: return launch_one<CLS_NET16, CHECK>(a, max_blocks, s);
+        case CLS_NET32: return launch_one<CLS_NET32, CHECK>(a, max_blocks, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
-    if (a.count <= 0) return hipSuccess;
-    switch (cls) {
-        case CLS_FULL: return launch_one<CLS_FULL>(a, max_blocks, s);
-        case CLS_NET1: return launch_one<CLS_NET1>(a, max_blocks, s);
-        case CLS_NET2: return launch_one<CLS_NET2>(a, max_blocks, s);
-        case CLS_NET4: return launch_one<CLS_NET4>(a, max_blocks, s);
-        case CLS_NET8: return launch_one<CLS_NET8>(a, max_blocks, s);
-        case CLS_NET16: return launch_one<CLS_NET16>(a, max_blocks, s);
-        case CLS_NET32: return launch_one<CLS_NET32>(a, max_blocks, s);
-        default: return hipErrorInvalidValue;
-    }
+    return launch_class<false>(cls, a, max_blocks, s);
+}
+
+hipError_t launch_check_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
+    if (!a.guess || !a.path || !a.rho) return hipErrorInvalidValue;
+    return launch_class<true>(cls, a, max_blocks, s);
 }
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t s) {

@@ -414,3 +414,16 @@ def random_problem(seed: int, n_u: int, n_m: int, n_f: int, density: float,
     M0 = rng.normal(0.0, 0.5, size=(n_m, n_f)).astype(np.float32)
     return Problem(f"random{seed}", n_u, n_m, n_f, row_ptr, cols.astype(np.int32),
                    val.astype(np.float32), lam, budget[0], budget[1], min_keep, 5, M0, U0, V0)
+
+
+def foldin_init_params(seed: int, n_f: int, hidden: int) -> np.ndarray:
+    """Seeded initial weights of the fold-in network, packed W1 [hidden x n_f],
+    c1, W2 [hidden x hidden], c2, W3 [n_f x hidden], c3: weights uniform in
+    +-1/sqrt(fan_in), biases zero (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((hidden, n_f), (hidden, hidden), (n_f, hidden)):
+        lim = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,313 @@
+"""Learned fold-in on the GPU against the FP64 oracle: forward, gradients,
+AdamW, the residual check with its exact fallback, and what a trained network
+gains over an untrained one and over a constant answer.
+
+Tolerances.  FP32 mode (FP32 MFMA operands): network outputs 1e-5 and
+gradients 1e-4 relative (Frobenius, per parameter block).  BF16 mode: operands
+rounded to bf16 (unit roundoff u = 2^-8) with FP32 accumulation; a product of
+two rounded operands is off by at most 2u relative, so sums with a
+cancellation ratio of a few stay within 3e-2; the tests use 3e-2 for outputs
+and gradients.  Residuals: the GPU forms b - A u with FP32 products and FP64
+sums; 1e-3 relative agreement with the FP64 oracle residual of the same u.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2509_18024_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def to_dev(prob):
+    import torch
+    return (torch.from_numpy(prob.row_ptr).cuda(), torch.from_numpy(prob.col_idx).cuda(),
+            torch.from_numpy(prob.val).cuda())
+
+
+def make_model(n_f, hidden, seed, precision, max_batch=512, max_train_rows=0, **kw):
+    import torch
+    from paper_2509_18024_amd import capi
+    from paper_2509_18024_amd.als import FoldIn
+    theta = synth.foldin_init_params(seed, n_f, hidden)
+    rng = np.random.default_rng(seed + 100)
+    # nonzero biases so that every term of the forward and backward pass is exercised
+    theta = theta + 0.05 * rng.standard_normal(theta.shape).astype(np.float32)
+    prec = capi.FOLDIN_FP32 if precision == "fp32" else capi.FOLDIN_BF16
+    m = FoldIn(n_f, torch.from_numpy(theta).cuda(), hidden=hidden, max_batch=max_batch, precision=prec,
+               max_train_rows=max_train_rows, **kw)
+    return m, theta
+
+
+CASES = [("fp32", 64, 256), ("bf16", 64, 256), ("fp32", 24, 72), ("bf16", 24, 72)]
+
+
+@gpu
+@pytest.mark.parametrize("precision,n_f,hidden", CASES)
+def test_forward_matches_oracle(precision, n_f, hidden):
+    import torch
+    from oracle import foldin as ofo
+    p = synth.random_problem(21, 300, 500, n_f, 0.06, heavy_rows=(4,))
+    note(f"[foldin forward] {precision} n_f={n_f} hidden={hidden} rows={p.n_u}")
+    m, theta = make_model(n_f, hidden, 1, precision, max_batch=128)  # several batches, ragged tail
+    rp, ci, v = to_dev(p)
+    M = torch.from_numpy(p.M0).cuda()
+    out = m.forward(M, rp, ci, v, n=p.n_u)
+    torch.cuda.synchronize()
+    x = ofo.bag(p.M0, p.row_ptr, p.col_idx, p.val, range(p.n_u))
+    ref, _ = ofo.forward(theta.astype(np.float64), x, n_f, hidden)
+    err = rel(out.cpu().numpy(), ref)
+    note(f"  rel err {err:.2e}")
+    assert err <= (1e-5 if precision == "fp32" else 3e-2)
+    # an explicit row list gives the same rows
+    rows = torch.arange(p.n_u - 1, -1, -3, dtype=torch.int32, device="cuda")
+    out2 = m.forward(M, rp, ci, v, rows=rows)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out[rows.long()])
+    m.close()
+
+
+@gpu
+@pytest.mark.parametrize("precision,n_f,hidden", CASES)
+def test_gradient_matches_oracle(precision, n_f, hidden):
+    import torch
+    from oracle import foldin as ofo
+    p = synth.random_problem(22, 700, 400, n_f, 0.05)
+    B = 600  # three split-K slabs, the last one ragged
+    note(f"[foldin grad] {precision} n_f={n_f} hidden={hidden} batch={B}")
+    m, theta = make_model(n_f, hidden, 2, precision, max_batch=B)
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(p.n_u, B, replace=False)).astype(np.int32)
+    target = rng.standard_normal((p.n_u, n_f)).astype(np.float32) * 0.3
+    rp, ci, v = to_dev(p)
+    M = torch.from_numpy(p.M0).cuda()
+    g, loss = m.grad(M, rp, ci, v, torch.from_numpy(target).cuda(), rows=torch.from_numpy(rows).cuda())
+    torch.cuda.synchronize()
+    x = ofo.bag(p.M0, p.row_ptr, p.col_idx, p.val, rows)
+    L, go = ofo.loss_and_grad(theta.astype(np.float64), x, target[rows].astype(np.float64), n_f, hidden)
+    gg = g.cpu().numpy()
+    tol = 1e-4 if precision == "fp32" else 3e-2
+    note(f"  loss gpu {loss.item():.6e} oracle {L:.6e}")
+    assert abs(loss.item() - L) <= tol * L
+    off = 0
+    for name, shp in ofo.shapes(n_f, hidden):
+        size = int(np.prod(shp))
+        e = rel(gg[off:off + size], go[off:off + size])
+        note(f"  {name}: rel err {e:.2e}")
+        assert e <= tol, name
+        off += size
+    m.close()
+
+
+@gpu
+def test_adamw_matches_oracle():
+    import torch
+    from oracle import foldin as ofo
+    n_f, hidden = 16, 40
+    m, theta = make_model(n_f, hidden, 3, "fp32", lr=1e-2, weight_decay=0.01)
+    P = theta.size
+    rng = np.random.default_rng(4)
+    th = theta.astype(np.float64)
+    mo, ve = np.zeros(P), np.zeros(P)
+    for t in (1, 2, 3):
+        g = rng.standard_normal(P).astype(np.float32)
+        m.adamw(torch.from_numpy(g).cuda())
+        th, mo, ve = ofo.adamw(th, g.astype(np.float64), mo, ve, t, lr=1e-2, wd=0.01)
+    got = m.params().cpu().numpy()
+    err = np.abs(got - th).max()
+    note(f"[foldin adamw] 3 steps, max abs diff {err:.2e}")
+    assert err <= 1e-5
+    m.close()
+
+
+@gpu
+def test_training_reduces_loss():
+    import torch
+    n_f, hidden = 32, 64
+    p = synth.random_problem(23, 2000, 300, n_f, 0.05)
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((n_f, n_f)) / math.sqrt(n_f)
+    from oracle import foldin as ofo
+    x = ofo.bag(p.M0, p.row_ptr, p.col_idx, p.val, range(p.n_u))
+    target = np.tanh(x @ W).astype(np.float32)  # a smooth function of the bag
+    m, _ = make_model(n_f, hidden, 4, "bf16", max_batch=256, max_train_rows=p.n_u)
+    rp, ci, v = to_dev(p)
+    losses = m.train(torch.from_numpy(p.M0).cuda(), rp, ci, v, torch.from_numpy(target).cuda(), epochs=8,
+                     batch=128, seed=9)
+    note(f"[foldin train] epoch losses {['%.4f' % l for l in losses]}")
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+    m.close()
+
+
+def query_problem(seed, n_f, budget, n_new=400, heavy_rows=(3, 17)):
+    return synth.random_problem(seed, n_new, 600, n_f, 0.06, budget=budget, heavy_rows=heavy_rows)
+
+
+@gpu
+@pytest.mark.parametrize("budget,prec", [((1, 10), 0), ((1, 1), 0), ((1, 4), 1)])
+def test_answer_check_and_exact_fallback(ora, budget, prec):
+    """Residuals match the oracle's for the same candidates; kept rows are the
+    network's answers; every other row is the exact regression."""
+    import torch
+    from oracle import foldin as ofo
+    from paper_2509_18024_amd.als import CoreALS
+    n_f = 64
+    p = query_problem(24, n_f, budget)
+    note(f"[foldin answer] r={budget[0]}/{budget[1]} precision={prec} users={p.n_u}")
+    q = CoreALS.from_problem(p, "cuda", budget=budget, precision=prec, users_only=True, heavy_min_degree=64,
+                             heavy_chunk=64)
+    m, _ = make_model(n_f, 128, 5, "bf16", max_batch=128)
+    M = torch.from_numpy(p.M0).cuda()
+    rp, ci, v = to_dev(p)
+    cand = m.forward(M, rp, ci, v, n=p.n_u).cpu().numpy()
+    # the candidates' residuals span a range; the median splits the users in two
+    rho_ref = np.array([ofo.relative_residual(
+        p.M0[p.col_idx[p.row_ptr[i]:p.row_ptr[i + 1]]], p.val[p.row_ptr[i]:p.row_ptr[i + 1]], p.lam,
+        ora.budget(int(p.row_ptr[i + 1] - p.row_ptr[i]), budget[0], budget[1], p.min_keep), cand[i])
+        for i in range(p.n_u)])
+    tol = float(np.median(rho_ref[np.isfinite(rho_ref)]))
+    U, path, rho, st = m.answer(q, M, tol=tol)
+    torch.cuda.synchronize()
+    U, path, rho = U.cpu().numpy(), path.cpu().numpy(), rho.cpu().numpy()
+    fin = np.isfinite(rho_ref)
+    assert np.array_equal(np.isfinite(rho), fin)
+    r_err = np.max(np.abs(rho[fin] - rho_ref[fin]) / rho_ref[fin])
+    note(f"  tol {tol:.3e}  kept {st.n_mlp} exact {st.n_exact} empty {st.n_empty}  residual rel diff {r_err:.2e}")
+    assert r_err <= 1e-3
+    clear = np.abs(rho_ref - tol) > 1e-3 * tol
+    assert np.array_equal(path[clear], (rho_ref[clear] > tol).astype(np.int32))
+    assert st.n_mlp == int((path == 0).sum()) and st.n_exact == int((path == 1).sum())
+    kept = path == 0
+    assert kept.any() and (~kept).any()
+    assert np.array_equal(U[kept], cand[kept])
+    Uo, _ = ora.half_sweep_rows(np.nonzero(~kept)[0], p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64),
+                                p.lam, budget[0], budget[1], p.min_keep)
+    e = rel(U[~kept], Uo)
+    note(f"  exact rows rel err {e:.2e}")
+    assert e <= 1e-4
+    q.close()
+    m.close()
+
+
+@gpu
+def test_answer_tolerance_extremes(ora):
+    """tol = 0 answers every user exactly (a users half-sweep); tol = inf keeps
+    every network answer except users without ratings (answer 0)."""
+    import torch
+    from paper_2509_18024_amd.als import CoreALS
+    n_f = 48
+    p = query_problem(25, n_f, (1, 10), n_new=300)
+    # one user without ratings
+    cut = p.row_ptr[1]
+    p.col_idx = np.delete(p.col_idx, np.s_[0:cut])
+    p.val = np.delete(p.val, np.s_[0:cut])
+    p.row_ptr = np.concatenate([[0], p.row_ptr[1:] - cut])
+    p.row_ptr[0] = 0
+    p.row_ptr[1] = 0
+    p.nnz = len(p.col_idx)
+    q = CoreALS.from_problem(p, "cuda", users_only=True)
+    m, _ = make_model(n_f, 64, 6, "bf16", max_batch=100)
+    M = torch.from_numpy(p.M0).cuda()
+    U0, path0, _, st0 = m.answer(q, M, tol=0.0)
+    Uh = q.half_sweep_users(M)
+    torch.cuda.synchronize()
+    assert st0.n_exact == p.n_u and st0.n_mlp == 0 and st0.n_empty == 1
+    d = rel(U0.cpu().numpy(), Uh.cpu().numpy())
+    note(f"[foldin tol=0] equal to the half-sweep: {bool(torch.equal(U0, Uh))}, rel diff {d:.1e}")
+    assert d <= 1e-6
+    Ui, pathi, rhoi, sti = m.answer(q, M, tol=math.inf)
+    rp, ci, v = to_dev(p)
+    cand = m.forward(M, rp, ci, v, n=p.n_u)
+    torch.cuda.synchronize()
+    assert sti.n_mlp == p.n_u - 1 and sti.n_exact == 1
+    assert pathi[0].item() == 1 and torch.all(Ui[0] == 0)
+    assert torch.equal(Ui[1:], cand[1:])
+    q.close()
+    m.close()
+
+
+@gpu
+def test_users_only_context_rejects_item_calls():
+    import torch
+    from paper_2509_18024_amd import capi
+    from paper_2509_18024_amd.als import CoreALS
+    p = synth.random_problem(26, 50, 40, 8, 0.3)
+    q = CoreALS.from_problem(p, "cuda", users_only=True)
+    U = torch.zeros(p.n_u, p.n_f, device="cuda")
+    with pytest.raises(capi.ALSError) as ei:
+        q.half_sweep_items(U)
+    assert ei.value.status == capi.ALS_E_STATE
+    with pytest.raises(capi.ALSError):
+        q.objective(U, torch.zeros(p.n_m, p.n_f, device="cuda"))
+    q.close()
+
+
+@gpu
+def test_trained_network_gains(ora):
+    """Train on users whose targets are their exact answers under frozen item
+    factors, then answer held-out users: the trained network's residuals are
+    far below an untrained network's and below the best constant answer (the
+    mean target), and more of its answers pass a given tolerance.  The
+    acceptance rate at 1e-3 is reported as measured."""
+    import torch
+    from oracle import foldin as ofo
+    from paper_2509_18024_amd.als import CoreALS, run_als
+    hidden = 256
+    base = synth.c3_batched(scale=0.005)
+    budget = (base.budget_num, base.budget_den)
+    note(f"[foldin gain] training users {base.n_u} items {base.n_m} nnz {base.nnz}")
+    tr = CoreALS.from_problem(base, "cuda", budget=budget)
+    _, M, _ = run_als(tr, torch.from_numpy(base.M0).cuda(), 5)
+    U_star = tr.half_sweep_users(M)  # exact answers of the training users under frozen M
+    rp, ci, v = to_dev(base)
+    m, _ = make_model(base.n_f, hidden, 7, "bf16", max_batch=1024, max_train_rows=base.n_u)
+    untrained = make_model(base.n_f, hidden, 7, "bf16", max_batch=1024)[0]
+    losses = m.train(M, rp, ci, v, U_star, epochs=40, batch=256, seed=1)
+    note(f"  losses first/last {losses[0]:.4e} {losses[-1]:.4e}")
+    assert losses[-1] < 0.5 * losses[0]
+    hrp, hci, hv = synth.c5_heldout(base, 2000)
+    n_new = len(hrp) - 1
+    q = CoreALS(n_new, base.n_m, base.n_f, torch.from_numpy(hrp).cuda(), torch.from_numpy(hci).cuda(),
+                torch.from_numpy(hv).cuda(), base.lam, budget, base.min_keep, users_only=True)
+    res = {}
+    for name, model in (("trained", m), ("untrained", untrained)):
+        _, path, rho, st = model.answer(q, M, tol=1e-3)
+        torch.cuda.synchronize()
+        res[name] = (rho.cpu().numpy(), st)
+    # constant answer: mean of the training targets, residuals from the oracle
+    ubar = U_star.mean(0).cpu().numpy().astype(np.float64)
+    Mh = M.cpu().numpy()
+    sample = np.random.default_rng(8).choice(n_new, 300, replace=False)
+    rho_const = []
+    for i in sample:
+        b, e = hrp[i], hrp[i + 1]
+        s = ora.budget(int(e - b), budget[0], budget[1], base.min_keep)
+        rho_const.append(ofo.relative_residual(Mh[hci[b:e]], hv[b:e], base.lam, s, ubar))
+    rho_const = np.array(rho_const)
+    med = {k: float(np.median(r[0][np.isfinite(r[0])])) for k, r in res.items()}
+    med_const = float(np.median(rho_const[np.isfinite(rho_const)]))
+    rt, ru = res["trained"][0], res["untrained"][0]
+    for t in (1e-3, 1e-2, 3e-2, 1e-1, 3e-1):
+        note(f"  tol {t:.0e}: kept trained {np.mean(rt <= t):.3f}  untrained {np.mean(ru <= t):.3f}  "
+             f"constant {np.mean(rho_const <= t):.3f}")
+    note(f"  median residual: trained {med['trained']:.3e}  untrained {med['untrained']:.3e}  "
+         f"constant {med_const:.3e};  kept at 1e-3: {res['trained'][1].n_mlp}/{n_new}")
+    assert med["trained"] < 0.25 * med["untrained"]
+    assert med["trained"] < 0.5 * med_const
+    q.close()
+    tr.close()
+    m.close()
+    untrained.close()

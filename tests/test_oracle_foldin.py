@@ -7,6 +7,7 @@ import pytest
 from scipy.stats import norm
 
 from oracle import foldin
+from paper_2509_18024_amd import synth
 
 
 def test_gelu_closed_forms():
@@ -33,7 +34,7 @@ def test_bag_hand_example():
 def test_gradient_matches_central_differences(seed):
     n_f, H, B = 5, 7, 4
     rng = np.random.default_rng(seed)
-    theta = foldin.init_params(seed, n_f, H).astype(np.float64) + 0.1 * rng.standard_normal(
+    theta = synth.foldin_init_params(seed, n_f, H).astype(np.float64) + 0.1 * rng.standard_normal(
         foldin.param_count(n_f, H))
     x = rng.standard_normal((B, n_f))
     tgt = rng.standard_normal((B, n_f))
@@ -59,3 +60,30 @@ def test_adamw_first_step_is_signed_lr():
 
 def test_param_count_matches_layer_sizes():
     assert foldin.param_count(64, 256) == 64 * 256 + 256 + 256 * 256 + 256 + 256 * 64 + 64 == 98880
+
+
+def test_relative_residual_pins():
+    import oracle
+    rng = np.random.default_rng(5)
+    n, nf, lam = 40, 6, 0.05
+    X = rng.standard_normal((n, nf))
+    y = rng.standard_normal(n)
+    # full data: the system is the ridge normal equation, solved independently by lstsq
+    Xa = np.vstack([X, math.sqrt(lam * n) * np.eye(nf)])
+    ya = np.concatenate([y, np.zeros(nf)])
+    u_ridge = np.linalg.lstsq(Xa, ya, rcond=None)[0]
+    assert foldin.relative_residual(X, y, lam, n, u_ridge) < 1e-12
+    assert foldin.relative_residual(X, y, lam, n, np.zeros(nf)) == 1.0
+    # core system: the oracle's own core solve satisfies it; a perturbed answer does not
+    s = 4
+    u, st = oracle.core_row(X, y, lam, s)
+    assert st == 0
+    assert foldin.relative_residual(X, y, lam, s, u) < 1e-12
+    assert foldin.relative_residual(X, y, lam, s, u * 1.01) > 1e-3
+    # a sketch that keeps one entry per column: A has the hand-computable form
+    A, b = foldin.core_system(X, y, lam, 1)
+    k = np.argmax(np.abs(X), axis=0)
+    for a in range(nf):
+        np.testing.assert_allclose(A[a], X[k[a], a] * X[k[a]] + lam * n * np.eye(nf)[a], rtol=1e-14)
+        assert abs(b[a] - X[k[a], a] * y[k[a]]) < 1e-14
+    assert foldin.relative_residual(np.zeros((0, nf)), np.zeros(0), lam, 0, np.ones(nf)) == math.inf
