@@ -153,7 +153,7 @@ def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, preci
     log(f"{tag}: r={res['budget']} {res['precision']} sweep {ms:.3f} ms (graph replay {graph_ms:.3f}), "
         f"{res['solves_per_s']:.3e} solves/s, "
         f"rmse {obj['rmse']:.5f} after {warmup + 2 * steps} it, init {init_s:.2f}s, schedule {cfg}")
-    return als, res
+    return als, res, M
 
 
 def cpu_baseline(prob, target_s=12.0, seed=7):
@@ -227,6 +227,114 @@ def sampled_parity(torch, als, prob, dev, seed=11):
             "pass": bool(eu <= 1e-4 and em <= 1e-4)}
 
 
+def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3, hidden=256, batch=1024):
+    """Learned fold-in on C5: train on every training user's exact answer under
+    the final item factors, then answer held-out users arriving in uneven
+    batches, with the network (answers kept when the relative residual is
+    <= tol, exact solves otherwise) and exact-only, and compare."""
+    from paper_2509_18024_amd import synth
+    from paper_2509_18024_amd.als import CoreALS, FoldIn
+    rp, ci, v = gpu_csr
+    budget = (1, 10)
+    with torch.cuda.stream(stream):
+        U_star = head_als.half_sweep_users(M)
+        theta = torch.from_numpy(synth.foldin_init_params(0, prob.n_f, hidden)).to(dev)
+        net = FoldIn(prob.n_f, theta, hidden=hidden, max_batch=16384, max_train_rows=prob.n_u, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        losses = net.train(M, rp, ci, v, U_star, epochs=args.foldin_epochs, batch=batch, seed=1)
+        stream.synchronize()
+        train_s = time.perf_counter() - t0
+        log(f"fold-in trained {args.foldin_epochs} epochs in {train_s:.1f}s, losses {losses}")
+        del U_star
+        # held-out users of C5 in arrival batches; their CSR slices are prepared
+        # before timing
+        hrp, hci, hv = synth.c5_heldout(prob, args.foldin_new_users)
+        sizes = synth.arrival_batches(len(hrp) - 1)
+        batches = []
+        u0 = 0
+        for b in sizes:
+            lo, hi = int(hrp[u0]), int(hrp[u0 + b])
+            batches.append((b, torch.from_numpy(hrp[u0:u0 + b + 1] - lo).to(dev),
+                            torch.from_numpy(hci[lo:hi]).to(dev), torch.from_numpy(hv[lo:hi]).to(dev)))
+            u0 += b
+        stream.synchronize()
+
+        def run(with_net):
+            outs, rhos, paths, kept = [], [], [], 0
+            stream.synchronize()
+            t = time.perf_counter()
+            for b, brp, bci, bv in batches:
+                q = CoreALS(b, prob.n_m, prob.n_f, brp, bci, bv, prob.lam, budget, prob.min_keep,
+                            1, validate=False, stream=stream, users_only=True)
+                if with_net:
+                    U, path, rho, st = net.answer(q, M, tol=tol, stats=False)
+                    rhos.append(rho)
+                    paths.append(path)
+                else:
+                    U = q.half_sweep_users(M)
+                outs.append(U)
+                q.close()
+            stream.synchronize()
+            return time.perf_counter() - t, outs, rhos, paths
+
+        run(True)  # warm-up of every code path
+        t_net, U_net, rhos, paths = run(True)
+        t_exact, U_ex, _, _ = run(False)
+        rho = torch.cat(rhos).cpu().numpy()
+        path = torch.cat(paths).cpu().numpy()
+        Un = torch.cat(U_net)
+        Ue = torch.cat(U_ex)
+        kept = path == 0
+        diff = (Un - Ue).norm(dim=1) / Ue.norm(dim=1).clamp_min(1e-30)
+        fin = rho[np.isfinite(rho)]
+        n_new = len(hrp) - 1
+        net.close()
+    return {
+        "train": {"users": prob.n_u, "epochs": args.foldin_epochs, "batch": batch, "hidden": hidden,
+                  "precision": "bf16 operands, fp32 accumulate/master weights", "seconds": train_s,
+                  "loss_per_epoch": losses},
+        "heldout": {"users": n_new, "nnz": int(hrp[-1]), "batches": len(sizes), "tol": tol,
+                    "kept_by_network": int(kept.sum()), "acceptance": float(kept.mean()),
+                    "users_per_s_network_path": n_new / t_net, "users_per_s_exact_only": n_new / t_exact,
+                    "speedup_vs_exact_only": t_exact / t_net,
+                    "residual_quantiles": {q: float(np.quantile(fin, q)) for q in (0.1, 0.5, 0.9)},
+                    "acceptance_if_tol": {str(t): float(np.mean(rho <= t)) for t in (1e-2, 3e-2, 1e-1, 3e-1)},
+                    "kept_answer_rel_diff_to_exact_max": float(diff[torch.from_numpy(kept).to(dev)].max().item())
+                    if kept.any() else None,
+                    "exact_answers_identical": bool(torch.equal(Un[torch.from_numpy(~kept).to(dev)],
+                                                                Ue[torch.from_numpy(~kept).to(dev)]))},
+    }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "paper_2509_18024_amd", "tuning", "hbm_traffic_gfx950.json")
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the HIP sources: counters taken on other sources are stale."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2509_18024_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_group: str):
+    """HBM bytes per launch of a kernel group from the committed rocprofv3
+    counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor),
+    or None when they were taken on other kernel sources or another group."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != kernel_source_digest() or t.get("kernel_group") != kernel_group:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=3):
     """A plain elementwise kernel (negation) that reads nbytes and writes nbytes
     once per launch: the known-size reference for the HBM byte counters."""
@@ -250,6 +358,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="time only r = 1/10 (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
+    ap.add_argument("--no-foldin", action="store_true", help="skip the learned fold-in section")
+    ap.add_argument("--foldin-epochs", type=int, default=5)
+    ap.add_argument("--foldin-new-users", type=int, default=100_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB float32 read+write kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -307,10 +418,11 @@ def main():
     head_als = None
     for tag, b, prec in variants:
         cfg = schedules["full" if b[0] == b[1] else "core"]
-        als, res = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg)
+        als, res, M_fin = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg)
         results[tag] = res
         if tag == HEAD:
             head_als = als
+            head_M = M_fin
         else:
             als.close()
             del als
@@ -338,7 +450,7 @@ def main():
     tfl = w["flops"] / (sweep_ms_k / 1000.0) / 1e12
     kname = f"{capi.PROF_NAMES[c]} ({'users' if sd == 0 else 'items'})"
     roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "kernel": kname, "avg_launch_ms": avg_ms, "launches_per_sweep": launches / args.steps,
                 "algorithmic_bytes_per_launch": w["bytes"] / (launches / args.steps),
                 "algorithmic_flops_per_launch": w["flops"] / (launches / args.steps), "fp32_tflops": tfl,
@@ -353,6 +465,12 @@ def main():
             "ms_per_sweep": msw, "launches_per_sweep": n_l / args.steps,
             "avg_launch_ms": am, "rows": ww["rows"], "nnz": ww["nnz"],
             "GB/s": ww["bytes"] / (msw / 1e3) / 1e9, "TFLOP/s": ww["flops"] / (msw / 1e3) / 1e12}
+
+    foldin = None
+    if not args.no_foldin:
+        log("fold-in: training on the users' exact answers, then answering held-out users ...")
+        foldin = foldin_report(torch, prob, gpu_csr, head_als, head_M, stream, dev, args)
+        log(f"fold-in: {json.dumps(foldin)}")
 
     parity = None
     if not args.no_parity:
@@ -402,6 +520,7 @@ def main():
                                  if full else None),
         "per_kernel": per_kernel,
         "parity_sampled_full_size": parity,
+        "foldin": foldin,
     }
     print(json.dumps(line), flush=True)
 

@@ -215,9 +215,7 @@ def test_answer_tolerance_extremes(ora):
     p.col_idx = np.delete(p.col_idx, np.s_[0:cut])
     p.val = np.delete(p.val, np.s_[0:cut])
     p.row_ptr = np.concatenate([[0], p.row_ptr[1:] - cut])
-    p.row_ptr[0] = 0
-    p.row_ptr[1] = 0
-    p.nnz = len(p.col_idx)
+    assert p.row_ptr[1] == 0 and p.nnz == len(p.col_idx)
     q = CoreALS.from_problem(p, "cuda", users_only=True)
     m, _ = make_model(n_f, 64, 6, "bf16", max_batch=100)
     M = torch.from_numpy(p.M0).cuda()
