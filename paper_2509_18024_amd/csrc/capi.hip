@@ -213,6 +213,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.partials = c->partials;
         h.resid = c->resid;
         h.refine = 0;
+        h.keep = c->bf16 ? 1 : 0;
         h.fp64res = c->fp64res ? 1 : 0;
         h.stats = c->stats;
         h.queue = queues + CLS_HEAVY;

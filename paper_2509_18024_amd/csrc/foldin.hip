@@ -92,7 +92,7 @@ __device__ __forceinline__ float load_b(const GemmArgs &g, int k, int n, bool ok
 // and rows 8 (r / 4) + 4 (l / 32) + r % 4 of accumulator r.
 template <bool BF16, int EPI>
 __global__ __launch_bounds__(G_WAVES * 64) void k_gemm(GemmArgs g, int k_per_split) {
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int l = lane & 31, h = lane >> 5;
     const int m0 = blockIdx.y * 64 + 32 * (w & 1);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(G_WAVES * 64) void k_gemm(GemmArgs g, int k_per_spl
 __global__ __launch_bounds__(WPB * 64) void k_bag(const int64_t *ptr, const int32_t *items, const float *vals,
                                                   const int32_t *rows, int64_t row_begin, int64_t nrows,
                                                   const float *M, int nf, float *out) {
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int lc = min(lane, nf - 1);
     for (int64_t b = (int64_t)blockIdx.x * WPB + w; b < nrows; b += (int64_t)gridDim.x * WPB) {

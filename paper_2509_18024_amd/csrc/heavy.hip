@@ -23,8 +23,9 @@
 // partial systems from bf16 MFMA tiles with FP32 accumulation) and add one
 // step of iterative refinement: k_heavy_resid forms the partial residuals
 // X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
-// second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the same
-// (re-factored) matrix and returns u + d.
+// second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the LU
+// factors the first solve kept (in the row's first partial slot) and returns
+// u + d.
 //
 // Fold-in answers (check mode) add k_heavy_check / k_heavy_check_reduce,
 // the relative residual of a candidate answer from per-chunk shares, before
@@ -37,16 +38,19 @@ namespace coreals {
 
 namespace {
 
-constexpr int HS_THREADS = 256;
+// Eight waves per heavy row and 32 gathers in flight per wave: the passes are
+// bound by the latency of the row gathers, so they need many loads in flight.
+constexpr int HS_THREADS = 512;
 constexpr int HS_WAVES = HS_THREADS / 64;
+constexpr int HS_BATCH = 32;
 
 struct HeavySelLds {
     // Narrow rows (n < 65536): bins 2j, 2j+1 of column a share word [j][a] as
     // two 16-bit counters.  Wide rows: word [d - dlo][a] is the 32-bit count of
     // digit d within the half range [dlo, dlo + 128) being counted.
     uint32_t hist[128][64];
-    int ckey[64][HEAVY_CAP];
-    int cpos[64][HEAVY_CAP];
+    int ckey[64][HEAVY_CAP + 1];  // padded: column a's list starts in bank a
+    int cpos[64][HEAVY_CAP + 1];
     int ccnt[64];
     int prefix[64];
     int rem[64];
@@ -74,31 +78,46 @@ __device__ __forceinline__ int heavy_key(const float *other, int col, int lane, 
 // column's prefix, count digit d = bits [shift, shift + width) if d lies in
 // [dlo, dhi).  Waves take interleaved chunks of 64 positions; lane a reads
 // column a (one 256-byte factor row per load instruction).
+template <bool WIDE, bool FIRST>
 __device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const float *other, int nf,
                                                 int64_t beg, int n, int shift, int width, int hmask, int dlo,
-                                                int dhi, bool wide, int w, int lane) {
+                                                int dhi, int w, int lane) {
     const int pre = S.prefix[lane];
     const bool act = !S.done[lane] && !S.found[lane];
     const int dmask = (1 << width) - 1;
     for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
         const int m = min(64, n - c0);
         const int colv = lane < m ? idx[beg + c0 + lane] : 0;
-        // 16 gathers in flight per batch, then the 16 keys are counted
-        for (int j0 = 0; j0 < m; j0 += 16) {
-            int key[16];
+        // HS_BATCH gathers in flight per batch, then their keys are counted
+        for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
+            int key[HS_BATCH];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < HS_BATCH; ++j) {
                 // positions past m read factor row colv = 0 (valid) and are dropped
                 const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
                 const int kk = heavy_key(other, col, lane, nf);
-                key[j] = (j0 + j < m) ? kk : -1;
+                if constexpr (FIRST) key[j] = kk;
+                else key[j] = (j0 + j < m) ? kk : -1;
+            }
+            if constexpr (FIRST) {
+                // first pass of a narrow row: every column is open and every
+                // key counts, by its exponent byte (bits 30..23); a branch-free
+                // add, skipped only past the row's end (a uniform test)
+#pragma unroll
+                for (int j = 0; j < HS_BATCH; ++j) {
+                    if (j0 + j < m) {
+                        const int d = key[j] >> 23;
+                        atomicAdd(&S.hist[d >> 1][lane], 1u << ((d & 1) << 4));
+                    }
+                }
+                continue;
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < HS_BATCH; ++j) {
                 if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
                     const int d = (key[j] >> shift) & dmask;
                     if (d >= dlo && d < dhi) {
-                        if (wide) atomicAdd(&S.hist[d - dlo][lane], 1u);
+                        if constexpr (WIDE) atomicAdd(&S.hist[d - dlo][lane], 1u);
                         else atomicAdd(&S.hist[d >> 1][lane], 1u << ((d & 1) << 4));
                     }
                 }
@@ -113,6 +132,8 @@ __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int
     if (S.done[a] || S.found[a]) return;
     int cum = S.cum[a], dsel = -1, below = 0, hsel = 0;
     const int rem = S.rem[a];
+    // unrolled so that the LDS reads of several digits are in flight together
+#pragma unroll 16
     for (int d = dhi - 1; d >= dlo; --d) {
         const int h = wide ? (int)S.hist[d - dlo][a] : (int)((S.hist[d >> 1][a] >> ((d & 1) << 4)) & 0xFFFFu);
         if (cum < rem && cum + h >= rem) {
@@ -140,7 +161,7 @@ __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int
 __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_t row_begin) {
     __shared__ HeavySelLds S;
     const int tid = threadIdx.x;
-    const int w = tid >> 6;
+    const int w = wave_index();
     const int lane = tid & 63;
     const int nf = a.nf;
     __shared__ int64_t next_t;
@@ -190,7 +211,15 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
                 const int dhi = wide ? (sub == 0 ? nd : nd / 2) : nd;
                 for (int q = tid; q < 128 * 64; q += HS_THREADS) (&S.hist[0][0])[q] = 0u;
                 __syncthreads();
-                heavy_hist_pass(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, wide, w, lane);
+                if (wide)
+                    heavy_hist_pass<true, false>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
+                                                 lane);
+                else if (pass == 0)
+                    heavy_hist_pass<false, true>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
+                                                 lane);
+                else
+                    heavy_hist_pass<false, false>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
+                                                  lane);
                 __syncthreads();
                 if (tid < 64) heavy_pick(S, tid, shift, dlo, dhi, wide);
                 __syncthreads();
@@ -223,16 +252,16 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
             for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
                 const int m = min(64, n - c0);
                 const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
-                for (int j0 = 0; j0 < m; j0 += 16) {
-                    int key[16];
+                for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
+                    int key[HS_BATCH];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) {
+                    for (int j = 0; j < HS_BATCH; ++j) {
                         const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
                         const int kk = heavy_key(a.other, col, lane, nf);
                         key[j] = (j0 + j < m) ? kk : -1;
                     }
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) {
+                    for (int j = 0; j < HS_BATCH; ++j) {
                         if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
                             const int slot = atomicAdd(&S.ccnt[lane], 1);
                             if (slot < HEAVY_CAP) {
@@ -244,20 +273,21 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
                 }
             }
             __syncthreads();
-            if (tid < 64 && !S.done[tid]) {
-                const int m = min(S.ccnt[tid], HEAVY_CAP);
-                const int want = S.rem[tid] - 1;  // rank from the top, 0-based
-                for (int x = 0; x < m; ++x) {
-                    const int kx = S.ckey[tid][x], px = S.cpos[tid][x];
-                    int rank = 0;
-                    for (int y = 0; y < m; ++y) {
-                        const int ky = S.ckey[tid][y], py = S.cpos[tid][y];
-                        rank += (ky > kx) || (ky == kx && py < px);
-                    }
-                    if (rank == want) {
-                        S.T[tid] = kx;
-                        S.K[tid] = px;
-                    }
+            // candidate x of column c is ranked by thread (c, x); exactly one
+            // candidate per column has the wanted rank, so T and K get one writer
+            for (int q = tid; q < 64 * HEAVY_CAP; q += HS_THREADS) {
+                const int c = q & 63, x = q >> 6;
+                const int m = min(S.ccnt[c], HEAVY_CAP);
+                if (S.done[c] || x >= m) continue;
+                const int kx = S.ckey[c][x], px = S.cpos[c][x];
+                int rank = 0;
+                for (int y = 0; y < m; ++y) {
+                    const int ky = S.ckey[c][y], py = S.cpos[c][y];
+                    rank += (ky > kx) || (ky == kx && py < px);
+                }
+                if (rank == S.rem[c] - 1) {  // rank from the top, 0-based
+                    S.T[c] = kx;
+                    S.K[c] = px;
                 }
             }
         } else {
@@ -297,7 +327,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
 
 __global__ __launch_bounds__(WPB * 64) void k_heavy_gram(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
@@ -329,7 +359,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram(HeavyArgs a, int64_t pa
 __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
                                                           int64_t pair_base) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane0 = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
@@ -341,6 +371,10 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        const float lamn = (float)((double)a.lam * (double)n);
+        // the first pair's partial slot holds the kept LU factors between the
+        // two solves (its partial system has been summed by then)
+        float *fac = a.partials + (a.pair_off[slot] - pair_base) * (int64_t)(NF + 1) * 64;
         float A[NF];
         float rhs = 0.f;
 #pragma unroll
@@ -351,26 +385,24 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
             for (int b = 0; b < NF; ++b) A[b] += src[b * 64 + lane];
             rhs += src[NF * 64 + lane];
         }
-        const float lamn = (float)((double)a.lam * (double)n);
         finish_system(A, rhs, lamn, lane, a.nf);
         float u = 0.f;
         const bool core = s < n;
-        if (a.refine) {
-            // second solve: rho = sum of chunk residuals - lambda n u, then u + A^-1 rho
-            const float u0 = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
-            double rho = 0.0;
-            for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p)
-                rho += a.resid[(p - pair_base) * 64 + lane];
-            rho -= (double)a.lam * (double)n * (double)u0;
-            if (lane >= a.nf) rho = 0.0;
-            float d = 0.f;
-            const bool ok = solve<true>(A, (float)rho, lane, a.nf, system_tol(A, a.nf), d, L);
-            if (!ok) continue;  // the first solve already used the full-data fallback
-            if (a.fp64res && lane == 0) atomicAdd(&a.stats[ST_FP64RES], 1ull);
-            if (lane < a.nf) a.out[i * a.nf + lane] = u0 + d;
-            continue;
+        bool ok;
+        if (a.keep) {
+            // a refinement step follows: keep the factors for it
+            int my_step;
+            float r[1] = {rhs};
+            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step);
+            if (ok) {
+                u = lu_back(A, r, lane, my_step, L);
+#pragma unroll
+                for (int b = 0; b < NF; ++b) fac[b * 64 + lane] = A[b];
+            }
+            fac[NF * 64 + lane] = __int_as_float(ok ? my_step : -1);
+        } else {
+            ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         }
-        bool ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         if (!ok) {
             u = 0.f;
             if (core) {
@@ -388,6 +420,40 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
     }
 }
 
+// Refinement step of a heavy row, with the LU factors its first solve kept:
+// u + A^-1 (rho - lambda n u), rho = sum of the chunk residuals.
+__global__ __launch_bounds__(WPB * 64) void k_heavy_refine(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
+                                                           int64_t pair_base) {
+    __shared__ WaveLds lds[WPB];
+    const int w = wave_index();
+    const int lane0 = threadIdx.x & 63;
+    WaveLds &L = lds[w];
+    for (int64_t slot = slot_begin + (int64_t)blockIdx.x * WPB + w; slot < slot_end;
+         slot += (int64_t)gridDim.x * WPB) {
+        const int lane = opaque_lane(lane0);
+        const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
+        const int n = (int)(a.ptr[i + 1] - a.ptr[i]);
+        const float *fac = a.partials + (a.pair_off[slot] - pair_base) * (int64_t)(NF + 1) * 64;
+        const int my_step = __float_as_int(fac[NF * 64 + lane]);
+        if (my_step < 0) continue;  // the first solve used the full-data fallback
+        float A[NF];
+#pragma unroll
+        for (int b = 0; b < NF; ++b) A[b] = fac[b * 64 + lane];
+        const float u0 = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
+        double rho = 0.0;
+        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p)
+            rho += a.resid[(p - pair_base) * 64 + lane];
+        rho -= (double)a.lam * (double)n * (double)u0;
+        if (lane >= a.nf) rho = 0.0;
+        float r[1] = {(float)rho};
+        fwd_all_u<1>(std::make_integer_sequence<int, NF>{}, A, r, my_step);
+        const float d = lu_back(A, r, lane, my_step, L);
+        if (a.fp64res && lane == 0) atomicAdd(&a.stats[ST_FP64RES], 1ull);
+        if (lane < a.nf) a.out[i * a.nf + lane] = u0 + d;
+    }
+}
+
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
@@ -399,7 +465,7 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 // tile and rows 8(r/4) + 4(l/32) + r%4 in accumulator r.
 __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int m = lane & 31, h = lane >> 5;
     WaveLds &L = lds[w];
@@ -483,7 +549,7 @@ template <bool FP64>
 __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     using acc_t = typename std::conditional<FP64, double, float>::type;
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
@@ -538,7 +604,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t p
 // (FP64 sums), into resid[pair][0..63] and resid[pair][64..127].
 __global__ __launch_bounds__(WPB * 64) void k_heavy_check(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
@@ -572,7 +638,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_check(HeavyArgs a, int64_t p
 // when |b - A g| / |b| <= tol; otherwise marks the row for the exact solve.
 __global__ __launch_bounds__(WPB * 64) void k_heavy_check_reduce(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
                                                                  int64_t pair_base) {
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     for (int64_t slot = slot_begin + (int64_t)blockIdx.x * WPB + w; slot < slot_end;
          slot += (int64_t)gridDim.x * WPB) {
@@ -656,8 +722,12 @@ hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pai
 hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
                               hipStream_t s) {
     if (slot_end <= slot_begin) return hipSuccess;
-    hipLaunchKernelGGL(k_heavy_solve, dim3(blocks_for(slot_end - slot_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
-                       slot_begin, slot_end, pair_base);
+    if (a.refine)
+        hipLaunchKernelGGL(k_heavy_refine, dim3(blocks_for(slot_end - slot_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
+                           a, slot_begin, slot_end, pair_base);
+    else
+        hipLaunchKernelGGL(k_heavy_solve, dim3(blocks_for(slot_end - slot_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
+                           a, slot_begin, slot_end, pair_base);
     return hipGetLastError();
 }
 

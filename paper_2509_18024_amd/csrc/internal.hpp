@@ -44,6 +44,11 @@ enum RowClass : int {
     NCLASS = 8
 };
 
+// Index of the calling wavefront in its workgroup, as a wave-uniform value
+// (threadIdx.x alone is taken as divergent, which would put every row index
+// derived from it, and the loops it bounds, in vector registers).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __host__ __device__ inline int64_t budget_of(int64_t n, uint32_t num, uint32_t den, int32_t min_keep) {
     int64_t s = (n * (int64_t)num) / (int64_t)den;
     if (s < min_keep) s = min_keep;
@@ -146,6 +151,7 @@ struct HeavyArgs {
     float *partials;
     double *resid;            // [pair_cap * 128] refinement / check residual partials
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
+    int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // residual accumulated in FP64
     unsigned long long *stats;
     unsigned int *queue;      // heavy-row selection counter (nullptr: grid-stride)

@@ -283,7 +283,9 @@ __device__ __forceinline__ void finish_system(float (&A)[NF], float &rhs, float 
 // largest |entry| among rows not yet used, found by a DPP max); otherwise
 // row J is the pivot (symmetric positive definite systems).  The pivot row
 // reaches the other lanes through scalar broadcasts (v_readlane).
-template <bool PIVOT, int NR, int J>
+// KEEP: the multiplier of each eliminated row is stored in its column J (no
+// longer needed there), so that the factors can solve later right-hand sides.
+template <bool PIVOT, int NR, int J, bool KEEP>
 __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
                                             int &my_step, bool &ok) {
     int p;
@@ -303,6 +305,7 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     ok = ok && (J >= nf || fabsf(piv) > tol);
     const bool elim = active && lane != p;
     const float l = elim ? A[J] / piv : 0.f;
+    if constexpr (KEEP) A[J] = elim ? l : A[J];
     if (lane == p) my_step = J;
 #pragma unroll
     for (int c = J + 1; c < NF; ++c) A[c] = fmaf(-l, readlane_f(A[c], p), A[c]);
@@ -315,6 +318,7 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
                                             float *xs) {
     int p;
     if constexpr (PIVOT) {
+        asm volatile("" : "+v"(my_step));  // see fwd_step_u
         const uint64_t bal = __ballot(my_step == J);
         p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
         p = __builtin_amdgcn_readfirstlane(p);
@@ -330,10 +334,34 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
     }
 }
 
-template <bool PIVOT, int NR, int... J>
+template <bool PIVOT, int NR, bool KEEP, int... J>
 __device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR],
                                            int lane, int nf, float tol, int &my_step, bool &ok) {
-    (elim_step_u<PIVOT, NR, J>(A, rhs, lane, nf, tol, my_step, ok), ...);
+    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok), ...);
+}
+
+// Forward elimination of a new right-hand side with kept factors: at step J
+// the rows pivoted later (my_step > J) subtract their multiplier times the
+// pivot row's entry, exactly as during the factorisation.
+template <int NR, int J>
+__device__ __forceinline__ void fwd_step_u(const float (&A)[NF], float (&rhs)[NR], int my_step) {
+    // opaque per step: otherwise the 64 step masks of a loaded my_step are
+    // all computed up front and spilled
+    asm volatile("" : "+v"(my_step));
+    const uint64_t bal = __ballot(my_step == J);
+    int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+    p = __builtin_amdgcn_readfirstlane(p);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const float rp = readlane_f(rhs[q], p);
+        if (my_step > J) rhs[q] = fmaf(-A[J], rp, rhs[q]);
+    }
+}
+
+template <int NR, int... J>
+__device__ __forceinline__ void fwd_all_u(std::integer_sequence<int, J...>, const float (&A)[NF], float (&rhs)[NR],
+                                          int my_step) {
+    (fwd_step_u<NR, J>(A, rhs, my_step), ...);
 }
 
 template <bool PIVOT, int NR, int... J>
@@ -350,7 +378,7 @@ __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int la
                                         float (&x)[NR], WaveLds &L) {
     int my_step = NF;  // elimination step at which this lane's row was the pivot
     bool ok = true;
-    elim_all_u<PIVOT, NR>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
     if (!PIVOT) my_step = lane;
     if (!ok) return false;
     wave_sync();
@@ -370,6 +398,26 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
     const bool ok = solve_n<PIVOT, 1>(A, r, lane, nf, tol, x, L);
     if (ok) u = x[0];
     return ok;
+}
+
+// Pivoted LU that keeps its factors in A (multipliers below, U above the
+// pivots) and the lane's pivot step in my_step; returns false on a pivot of
+// the first nf steps <= tol.
+__device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lane, int nf, float tol, int &my_step) {
+    my_step = NF;
+    bool ok = true;
+    elim_all_u<true, 1, true>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    return ok;
+}
+
+// Back substitution of an eliminated right-hand side; x = component `lane`.
+__device__ __forceinline__ float lu_back(const float (&A)[NF], float (&rhs)[1], int lane, int my_step, WaveLds &L) {
+    wave_sync();
+    back_all_u<true, 1>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, my_step, L.urhs);
+    wave_sync();
+    const float x = L.urhs[lane];
+    wave_sync();
+    return x;
 }
 
 __device__ __forceinline__ float system_tol(const float (&A)[NF], int nf) {

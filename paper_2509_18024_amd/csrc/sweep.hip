@@ -38,7 +38,7 @@ __device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, in
 template <int CLS, bool CHECK>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane0 = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))
 // heavy rows take the cut computed beforehand by the heavy-row selection.
 __global__ __launch_bounds__(WPB * 64) void k_select(SelectArgs a) {
     __shared__ WaveLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     WaveLds &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
