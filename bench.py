@@ -180,12 +180,16 @@ def cpu_baseline(prob, target_s=12.0, seed=7):
         ti = time.perf_counter() - t
         return tu, ti
 
-    pu, pi = max(64, prob.n_u // 2000), max(16, prob.n_m // 2000)
-    tu, ti = run(pu, pi)
-    per_u, per_i = tu / pu, ti / pi
-    ku = int(min(prob.n_u, max(pu, 0.5 * target_s / max(per_u, 1e-9))))
-    ki = int(min(prob.n_m, max(pi, 0.5 * target_s / max(per_i, 1e-9))))
-    tu, ti = run(ku, ki)
+    # grow the sample until its measured time reaches about target_s (the
+    # first small runs also pay thread start-up, so one pilot underestimates)
+    ku, ki = max(64, prob.n_u // 2000), max(16, prob.n_m // 2000)
+    for _ in range(6):
+        tu, ti = run(ku, ki)
+        if tu + ti >= 0.7 * target_s or (ku == prob.n_u and ki == prob.n_m):
+            break
+        per_u, per_i = tu / ku, ti / ki
+        ku = int(min(prob.n_u, max(ku, 0.5 * target_s / max(per_u, 1e-9))))
+        ki = int(min(prob.n_m, max(ki, 0.5 * target_s / max(per_i, 1e-9))))
     sweep_s = tu * prob.n_u / ku + ti * prob.n_m / ki
     return {
         "value": (prob.n_u + prob.n_m) / sweep_s,
@@ -362,7 +366,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="time only r = 1/10 (profiling)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
     ap.add_argument("--no-foldin", action="store_true", help="skip the learned fold-in section")
     ap.add_argument("--foldin-epochs", type=int, default=5)

@@ -8,9 +8,9 @@
 //                   passes (exponent byte, top mantissa byte) the few keys that
 //                   share the threshold's 16-bit prefix are copied into LDS and
 //                   ranked exactly by (key desc, position asc); only if more
-//                   than HEAVY_CAP keys share it do two more radix passes and
-//                   a position pass run.  Three gathers of the row in the
-//                   common case.
+//                   than HEAVY_CAP keys share it do two more radix passes, and
+//                   a position pass where keys equal the threshold.  Three
+//                   gathers of the row in the common case.
 //   k_heavy_gram    one wavefront per (row, chunk of `chunk` entries) builds
 //                   the chunk's part of X*^T X and X*^T y (eq. core_ui) with
 //                   the row's cut, and stores it to scratch (column-major, so
@@ -48,9 +48,14 @@ struct HeavySelLds {
     // Narrow rows (n < 65536): bins 2j, 2j+1 of column a share word [j][a] as
     // two 16-bit counters.  Wide rows: word [d - dlo][a] is the 32-bit count of
     // digit d within the half range [dlo, dlo + 128) being counted.
-    uint32_t hist[128][64];
-    int ckey[64][HEAVY_CAP + 1];  // padded: column a's list starts in bank a
-    int cpos[64][HEAVY_CAP + 1];
+    // the candidate lists are used only after the last counting pass
+    union {
+        uint32_t hist[128][64];
+        struct {
+            int ckey[64][HEAVY_CAP + 1];  // padded: column a's list starts in bank a
+            int cpos[64][HEAVY_CAP + 1];
+        };
+    };
     int ccnt[64];
     int prefix[64];
     int rem[64];
@@ -291,27 +296,76 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
                 }
             }
         } else {
-            // all 31 bits resolved: T is the key itself; ties resolved by position
-            if (tid < 64 && !S.done[tid]) S.T[tid] = S.prefix[tid];
+            // all 31 bits resolved: T is the key itself.  Where more keys than
+            // needed equal T, the kept ones are the first `need` positions:
+            // the positions of the keys equal to T are collected by all waves
+            // (batched gathers) and ranked.
+            if (tid < 64) {
+                if (!S.done[tid]) S.T[tid] = S.prefix[tid];
+                S.ccnt[tid] = 0;
+            }
+            if (tid == 0) S.flag = 0;
             __syncthreads();
+            const bool tie = !S.done[lane] && S.ceq[lane] > S.rem[lane];
             if (w == 0) {
-                const bool tie = !S.done[lane] && S.ceq[lane] > S.rem[lane];
-                if (__ballot(tie) != 0ull) {
-                    const int T = S.T[lane], need = S.rem[lane];
-                    int cnt = 0, K = 0x7FFFFFFF;
-                    for (int c0 = 0; c0 < n; c0 += 64) {
-                        const int m = min(64, n - c0);
-                        const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
-                        for (int j = 0; j < m; ++j) {
-                            const int col = __builtin_amdgcn_readlane(colv, j);
-                            const int key = heavy_key(a.other, col, lane, nf);
-                            if (tie && key == T) {
-                                ++cnt;
-                                if (cnt == need) K = c0 + j;
+                const uint64_t any_tie = __ballot(tie);
+                if (lane == 0 && any_tie != 0ull) S.flag = 1;
+            }
+            __syncthreads();
+            if (S.flag) {
+                const int T = S.T[lane];
+                for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
+                    const int m = min(64, n - c0);
+                    const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
+                    for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
+                        int key[HS_BATCH];
+#pragma unroll
+                        for (int j = 0; j < HS_BATCH; ++j) {
+                            const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
+                            const int kk = heavy_key(a.other, col, lane, nf);
+                            key[j] = (j0 + j < m) ? kk : -1;
+                        }
+#pragma unroll
+                        for (int j = 0; j < HS_BATCH; ++j) {
+                            if (tie && key[j] == T) {
+                                const int slot = atomicAdd(&S.ccnt[lane], 1);
+                                if (slot < HEAVY_CAP) S.cpos[lane][slot] = c0 + j0 + j;
                             }
                         }
                     }
-                    if (tie) S.K[lane] = K;
+                }
+                __syncthreads();
+                for (int q = tid; q < 64 * HEAVY_CAP; q += HS_THREADS) {
+                    const int c = q & 63, x = q >> 6;
+                    const bool tie_c = !S.done[c] && S.ceq[c] > S.rem[c];
+                    const int m = S.ccnt[c];
+                    if (!tie_c || m > HEAVY_CAP || x >= m) continue;
+                    const int px = S.cpos[c][x];
+                    int rank = 0;
+                    for (int y = 0; y < m; ++y) rank += S.cpos[c][y] < px;
+                    if (rank == S.rem[c] - 1) S.K[c] = px;
+                }
+                __syncthreads();
+                if (w == 0) {
+                    // more equal keys than the lists hold: one wave walks the row
+                    const bool over = tie && S.ccnt[lane] > HEAVY_CAP;
+                    if (__ballot(over) != 0ull) {
+                        const int need = S.rem[lane];
+                        int cnt = 0, K = 0x7FFFFFFF;
+                        for (int c0 = 0; c0 < n; c0 += 64) {
+                            const int m = min(64, n - c0);
+                            const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
+                            for (int j = 0; j < m; ++j) {
+                                const int col = __builtin_amdgcn_readlane(colv, j);
+                                const int key = heavy_key(a.other, col, lane, nf);
+                                if (over && key == T) {
+                                    ++cnt;
+                                    if (cnt == need) K = c0 + j;
+                                }
+                            }
+                        }
+                        if (over) S.K[lane] = K;
+                    }
                 }
             }
         }

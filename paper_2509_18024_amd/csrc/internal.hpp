@@ -20,8 +20,9 @@ constexpr int NF = 64;
 constexpr int WPB = 4;
 // Rows of the design matrix staged in LDS per chunk.
 constexpr int CK = 64;
-// Keys per column the heavy-row selection ranks directly in LDS.
-constexpr int HEAVY_CAP = 32;
+// Keys per column the heavy-row selection ranks directly in LDS (the lists
+// share LDS with the radix histogram).
+constexpr int HEAVY_CAP = 62;
 // Defaults of the schedule (als_problem fields set to 0 select them).
 constexpr int DEFAULT_HEAVY_N = 1024;    // light rows have degree <= this
 constexpr int DEFAULT_CHUNK = 1024;      // entries per partial Gram of a heavy row

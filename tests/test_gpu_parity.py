@@ -390,6 +390,37 @@ def test_wide_row_selection_and_sweep(ora):
 
 
 @gpu
+def test_heavy_selection_full_radix_with_ties(ora):
+    """Factor magnitudes uniform in [1, 2) on a 2^-11 grid: in a row of 60000
+    ratings about 230 keys share the threshold's 16-bit prefix, more than the
+    candidate lists hold (all four radix passes run), and about 30 keys equal
+    the threshold itself (the tie pass by position)."""
+    import torch
+    rng = np.random.default_rng(31)
+    n_u, n_m, nf = 5, 60000, 8
+    rows = [np.arange(n_m)] + [np.sort(rng.choice(n_m, 2000, replace=False)) for _ in range(n_u - 1)]
+    rp = np.zeros(n_u + 1, np.int64)
+    np.cumsum([len(r) for r in rows], out=rp[1:])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(len(ci)).astype(np.float32)
+    M0 = ((1.0 + np.floor(rng.random((n_m, nf)) * 2048.0) / 2048.0)
+          * rng.choice([-1.0, 1.0], size=(n_m, nf))).astype(np.float32)
+    p = synth.Problem("grid", n_u, n_m, nf, rp, ci, val, 0.05, 1, 10, 1, 1, M0)
+    note("[full radix + ties] n=60000, magnitudes in [1, 2) on a 2^-11 grid")
+    als = make_als(p, heavy_min_degree=64)
+    sel_ptr, sel = als.core_select(0, torch.from_numpy(M0).cuda(), 0, n_u)
+    torch.cuda.synchronize()
+    rpo, rso = ora.core_select_rows(np.arange(n_u), rp, ci, M0.astype(np.float64), 1, 10, 1)
+    assert np.array_equal(sel_ptr.cpu().numpy(), rpo)
+    assert np.array_equal(sel.cpu().numpy(), rso)
+    U = als.half_sweep_users(torch.from_numpy(M0).cuda())
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(rp, ci, val, M0.astype(np.float64), 0.05, 1, 10, 1)
+    assert rel_fro(U.cpu().numpy(), Uo) <= 1e-4
+    als.close()
+
+
+@gpu
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("which", range(3))
 def test_bf16_refined_heavy_rows(ora, which, prec):
