@@ -420,6 +420,148 @@ __device__ __forceinline__ float lu_back(const float (&A)[NF], float (&rhs)[1], 
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// Light core rows with few entries (n <= WB_D): by the Woodbury identity the
+// solution of (lambda n E + W^T X) u = W^T y, with W the kept entries of X
+// (n x n_f), is u = (b - W^T z) / (lambda n), b = W^T y, where z solves the
+// n x n system G z = X b, G = lambda n E + X W^T.  The pivoted LU then has n
+// steps instead of n_f.  Used only while max_k |x_k|^2 <= WB_AMP lambda, which
+// bounds the cancellation in b - W^T z (error growth below WB_AMP).
+constexpr int WB_D = 32;
+constexpr float WB_AMP = 256.f;
+
+template <int J>
+__device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lane, int n, float tol, int &my_step,
+                                             bool &ok) {
+    if (J >= n) return;  // uniform: the system has n rows
+    const bool active = my_step == WB_D + 1;
+    const int cand = active ? __float_as_int(fabsf(G[J])) : -1;
+    const int mx = wave_max_key(cand);
+    const uint64_t bal = __ballot(active && cand == mx);
+    int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+    p = __builtin_amdgcn_readfirstlane(p);
+    const float piv = readlane_f(G[J], p);
+    ok = ok && fabsf(piv) > tol;
+    const bool elim = active && lane != p;
+    const float l = elim ? G[J] / piv : 0.f;
+    if (lane == p) my_step = J;
+#pragma unroll
+    for (int c = J + 1; c < WB_D; ++c) G[c] = fmaf(-l, readlane_f(G[c], p), G[c]);
+    t = fmaf(-l, readlane_f(t, p), t);
+}
+
+template <int J>
+__device__ __forceinline__ void wb_back_step(const float (&G)[WB_D], float &t, int lane, int n, int my_step,
+                                             float *zs) {
+    if (J >= n) return;
+    asm volatile("" : "+v"(my_step));
+    const uint64_t bal = __ballot(my_step == J);
+    int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+    p = __builtin_amdgcn_readfirstlane(p);
+    const float x = readlane_f(t, p) / readlane_f(G[J], p);
+    if (lane == 0) zs[J] = x;
+    if (my_step < J) t = fmaf(-G[J], x, t);
+}
+
+template <int... J>
+__device__ __forceinline__ bool wb_lu(std::integer_sequence<int, J...>, float (&G)[WB_D], float &t, int lane, int n,
+                                      float tol, float *zs) {
+    int my_step = WB_D + 1;
+    bool ok = true;
+    (wb_elim_step<J>(G, t, lane, n, tol, my_step, ok), ...);
+    if (!ok) return false;
+    (wb_back_step<WB_D - 1 - J>(G, t, lane, n, my_step, zs), ...);
+    return true;
+}
+
+// Woodbury solve of a staged light row (n <= WB_D rows of X in L.X, cut c of
+// the lane's column).  Returns false, leaving L.X untouched, when the guard
+// fails; returns false after masking L.X in place when G is singular (the
+// caller re-stages).  On success u is component `lane` of the solution.
+__device__ __forceinline__ bool woodbury_solve(WaveLds &L, const Cut &c, int lane, int n, int nf, float lam,
+                                               float lamn, bool &masked, float &u) {
+    masked = false;
+    // lane k holds design row k (rows n.. are the staged zero padding)
+    float xk[NF];
+    float nrm = 0.f;
+#pragma unroll
+    for (int b4 = 0; b4 < NF / 4; ++b4) {
+        const float4 v = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
+        xk[4 * b4 + 0] = v.x;
+        xk[4 * b4 + 1] = v.y;
+        xk[4 * b4 + 2] = v.z;
+        xk[4 * b4 + 3] = v.w;
+        nrm = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, nrm))));
+    }
+    const float mx = __int_as_float(wave_max_key(__float_as_int(nrm)));  // nrm >= 0
+    if (!(mx <= WB_AMP * lam)) return false;
+    // b_a = sum over kept k of x_ka y_k; then W = X with the unkept entries zeroed
+    float b = 0.f;
+    bool keep[WB_D];
+#pragma unroll
+    for (int k = 0; k < WB_D; ++k) {
+        const float x = L.X[k][lane];
+        keep[k] = k < n && kept(c, key_of(x), k);
+        if (keep[k]) b = fmaf(x, L.y[k], b);
+    }
+    if (lane >= nf) b = 0.f;
+    wave_sync();
+    masked = true;
+#pragma unroll
+    for (int k = 0; k < WB_D; ++k)
+        if (!keep[k]) L.X[k][lane] = 0.f;
+    L.urhs[lane] = b;
+    wave_sync();
+    // G row `lane` and t_lane = x_lane . b
+    float G[WB_D];
+    float t = 0.f;
+#pragma unroll
+    for (int b4 = 0; b4 < NF / 4; ++b4) {
+        const float4 bv = *reinterpret_cast<const float4 *>(&L.urhs[4 * b4]);
+        t = fmaf(xk[4 * b4 + 0], bv.x, t);
+        t = fmaf(xk[4 * b4 + 1], bv.y, t);
+        t = fmaf(xk[4 * b4 + 2], bv.z, t);
+        t = fmaf(xk[4 * b4 + 3], bv.w, t);
+    }
+#pragma unroll
+    for (int l = 0; l < WB_D; ++l) {
+        float g = 0.f;
+        if (l < n) {
+#pragma unroll
+            for (int b4 = 0; b4 < NF / 4; ++b4) {
+                const float4 wv = *reinterpret_cast<const float4 *>(&L.X[l][4 * b4]);
+                g = fmaf(xk[4 * b4 + 0], wv.x, g);
+                g = fmaf(xk[4 * b4 + 1], wv.y, g);
+                g = fmaf(xk[4 * b4 + 2], wv.z, g);
+                g = fmaf(xk[4 * b4 + 3], wv.w, g);
+            }
+        }
+        G[l] = g + (l == lane ? lamn : 0.f);
+    }
+    // rows n.. of the padded system are identity rows
+    if (lane >= n) {
+#pragma unroll
+        for (int l = 0; l < WB_D; ++l) G[l] = (l == lane) ? 1.f : 0.f;
+        t = 0.f;
+    }
+    float gm = 0.f;
+#pragma unroll
+    for (int l = 0; l < WB_D; ++l) gm = fmaxf(gm, fabsf(G[l]));
+    gm = __int_as_float(wave_max_key(__float_as_int(gm)));
+    const float tol = (float)n * 1.1920928955078125e-7f * gm;
+    float *zs = &L.urhs[NF];  // z_k, written by lane 0 of the back substitution
+    if (!wb_lu(std::make_integer_sequence<int, WB_D>{}, G, t, lane, n, tol, zs)) return false;
+    wave_sync();
+    // u_a = (b_a - sum over kept k of x_ka z_k) / (lambda n)
+    float s = b;
+#pragma unroll
+    for (int k = 0; k < WB_D; ++k)
+        if (k < n) s = fmaf(-L.X[k][lane], zs[k], s);
+    u = lane < nf ? s / lamn : 0.f;
+    wave_sync();
+    return true;
+}
+
 __device__ __forceinline__ float system_tol(const float (&A)[NF], int nf) {
     float m = 0.f;
 #pragma unroll

@@ -12,6 +12,10 @@
 //              pivot below n_f 2^-23 max|A| sends a core row to the full-data
 //              update.
 //
+// Rows of the two smallest network classes with at most 32 entries solve the
+// same system in its n x n Woodbury form (woodbury_solve), when the data
+// bound the cancellation that form incurs.
+//
 // The check variant (fold-in answers) inserts between 2 and 3 the relative
 // residual |b - A g| / |b| of a candidate g, formed matrix-free from the
 // staged rows (b - A g = X*^T (y - X g) - lambda n_i g), and skips 3 and 4
@@ -95,6 +99,19 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
             if (accept) {
                 if (lane < a.nf) a.out[i * a.nf + lane] = g;
                 continue;
+            }
+        }
+        if constexpr (!CHECK && (CLS == CLS_NET1 || CLS == CLS_NET2)) {
+            // few entries: the n x n Woodbury form of the same system
+            if (n <= WB_D && s > 0 && a.lam > 0.f) {
+                stage(L, r, 0, lane);  // the whole row is chunk 0
+                bool masked;
+                float uw;
+                if (woodbury_solve(L, c, lane, n, a.nf, a.lam, lamn, masked, uw)) {
+                    if (lane < a.nf) a.out[i * a.nf + lane] = uw;
+                    continue;
+                }
+                if (masked) r.staged = -1;  // L.X holds the masked rows: re-stage
             }
         }
         float A[NF];

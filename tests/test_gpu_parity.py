@@ -390,6 +390,36 @@ def test_wide_row_selection_and_sweep(ora):
 
 
 @gpu
+@pytest.mark.parametrize("budget,scale", [((1, 10), 0.1), ((1, 20), 0.08), ((1, 10), 0.35), ((1, 10), 0.45)])
+def test_small_rows_woodbury_form(ora, budget, scale):
+    """Rows of the two smallest network classes (n <= 32): their n x n Woodbury
+    form where max |x_k|^2 <= 256 lambda (scales 0.1, 0.08, 0.35), the 64 x 64
+    system where that bound fails (most rows at scale 0.45); all against the
+    oracle's direct solve.  (At scale 0.6 one row of this draw has condition
+    number 9e5 and |u| = 3e4, where no FP32 solve meets 1e-4.)"""
+    import torch
+    rng = np.random.default_rng(41)
+    n_u, n_m, nf = 3000, 800, 64
+    deg = rng.integers(1, 33, n_u)
+    rows = [np.sort(rng.choice(n_m, d, replace=False)) for d in deg]
+    rp = np.zeros(n_u + 1, np.int64)
+    np.cumsum(deg, out=rp[1:])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(len(ci)).astype(np.float32)
+    M0 = (scale * rng.standard_normal((n_m, nf))).astype(np.float32)
+    p = synth.Problem("small-rows", n_u, n_m, nf, rp, ci, val, 0.05, budget[0], budget[1], 1, 1, M0)
+    note(f"[small rows] r={budget[0]}/{budget[1]} factor scale {scale}")
+    als = make_als(p)
+    U = als.half_sweep_users(torch.from_numpy(M0).cuda())
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(rp, ci, val, M0.astype(np.float64), 0.05, budget[0], budget[1], 1)
+    err = rel_fro(U.cpu().numpy(), Uo)
+    note(f"  rel err {err:.2e}")
+    assert err <= 1e-4
+    als.close()
+
+
+@gpu
 def test_heavy_selection_full_radix_with_ties(ora):
     """Factor magnitudes uniform in [1, 2) on a 2^-11 grid: in a row of 60000
     ratings about 230 keys share the threshold's 16-bit prefix, more than the
