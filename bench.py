@@ -308,8 +308,10 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
                     "acceptance_if_tol": {str(t): float(np.mean(rho <= t)) for t in (1e-2, 3e-2, 1e-1, 3e-1)},
                     "kept_answer_rel_diff_to_exact_max": float(diff[torch.from_numpy(kept).to(dev)].max().item())
                     if kept.any() else None,
-                    "exact_answers_identical": bool(torch.equal(Un[torch.from_numpy(~kept).to(dev)],
-                                                                Ue[torch.from_numpy(~kept).to(dev)]))},
+                    # the check kernels solve without the Woodbury form of the smallest
+                    # rows, so exact answers agree to rounding, not bit for bit
+                    "exact_answer_rel_diff_max": float(diff[torch.from_numpy(~kept).to(dev)].max().item())
+                    if (~kept).any() else None},
     }
 
 
