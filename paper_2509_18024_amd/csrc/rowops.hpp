@@ -208,6 +208,42 @@ __device__ __forceinline__ void gram_range(WaveLds &L, RowCtx &r, const Cut &c, 
     }
 }
 
+// The same row of X*^T X and entry of X*^T y, visiting only the lane's kept
+// positions: per staged chunk each lane marks its kept positions in a 64-bit
+// mask, then walks them in ascending order (the wave iterates as often as its
+// busiest lane).  Only the zero products of the unkept positions are skipped,
+// so the sums equal gram_range's.
+__device__ __forceinline__ void gram_range_sparse(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+                                                  float (&A)[NF], float &rhs) {
+#pragma unroll
+    for (int b = 0; b < NF; ++b) A[b] = 0.f;
+    rhs = 0.f;
+    if (c.none) return;
+    for (int k0 = kb; k0 < ke; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, ke - k0);
+        uint64_t bits = 0;
+        for (int k = 0; k < m; ++k)
+            if (kept(c, key_of(L.X[k][lane]), k0 + k)) bits |= 1ull << k;
+        while (__ballot(bits != 0ull)) {
+            if (bits != 0ull) {
+                const int k = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1;
+                const float w = L.X[k][lane];
+#pragma unroll
+                for (int b4 = 0; b4 < NF / 4; ++b4) {
+                    const float4 xr = *reinterpret_cast<const float4 *>(&L.X[k][b4 * 4]);
+                    A[4 * b4 + 0] = fmaf(w, xr.x, A[4 * b4 + 0]);
+                    A[4 * b4 + 1] = fmaf(w, xr.y, A[4 * b4 + 1]);
+                    A[4 * b4 + 2] = fmaf(w, xr.z, A[4 * b4 + 2]);
+                    A[4 * b4 + 3] = fmaf(w, xr.w, A[4 * b4 + 3]);
+                }
+                rhs = fmaf(w, L.y[k], rhs);
+            }
+        }
+    }
+}
+
 // Matrix-free residual of a candidate solution g of the row's system, with
 // g_a parked in L.urhs[a]: over positions [kb, ke), lane a accumulates
 // rho_a = sum over kept k of x_ka (y_k - x_k . g) and b_a = sum over kept k of

@@ -7,7 +7,7 @@
 //              lane (lane a keeps the s largest keys of column a), the tie cut
 //              fixed by a position pass when the threshold key repeats.
 //   3. Gram:   row a of X*^T X and entry a of X*^T y (eq. core_ui), lambda n_i
-//              on the diagonal.
+//              on the diagonal; core rows visit only each column's kept rows.
 //   4. solve:  pivoted LU in registers, or LDL^T when s == n (eq. (U)).  A
 //              pivot below n_f 2^-23 max|A| sends a core row to the full-data
 //              update.
@@ -121,7 +121,8 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
         // singular): the full-data update of eq. (U)
 #pragma unroll 1
         for (int attempt = 0; attempt < 2; ++attempt) {
-            gram(L, r, c, lane, A, rhs);
+            if constexpr (kCore) gram_range_sparse(L, r, c, 0, n, lane, A, rhs);
+            else gram(L, r, c, lane, A, rhs);
             finish_system(A, rhs, lamn, lane, a.nf);
             const bool ok = solve<kCore>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
             if (ok) break;
