@@ -195,6 +195,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.idx = S.idx;
         h.val = S.val;
         h.other = other;
+        h.other_rows = side == 0 ? c->p.n_m : c->p.n_u;
         h.out = out;
         h.rows = S.perm + S.class_off[CLS_HEAVY];
         h.count = H.n_heavy;
@@ -541,6 +542,7 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
         h.ptr = S.ptr;
         h.idx = S.idx;
         h.other = other;
+        h.other_rows = side == 0 ? c->p.n_m : c->p.n_u;
         h.rows = nullptr;
         h.count = r1 - r0;
         h.nf = c->p.n_f;

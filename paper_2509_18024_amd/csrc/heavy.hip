@@ -72,63 +72,113 @@ __device__ __forceinline__ bool is_heavy_core(int n, int s, int heavy_n) {
     return class_of(n, s, heavy_n) == CLS_HEAVY && s < n;
 }
 
-// The load is unconditional (lane clamped to a valid column) so that a run of
-// these gathers stays in flight together; padded lanes get key 0.
-__device__ __forceinline__ int heavy_key(const float *other, int col, int lane, int nf) {
-    const int k = key_of(other[(size_t)col * nf + min(lane, nf - 1)]);
-    return lane < nf ? k : 0;
+// Factor-row gathers of the selection passes: lane a reads entry a of one
+// factor row per load instruction, as raw bits (every test below masks the
+// sign).  Padded lanes (a >= n_f) read column n_f - 1 and are never used.
+// With a buffer resource (factor matrices below 2^31 bytes) the row offset is
+// a scalar operand of the load, so a gather costs one readlane and one scalar
+// multiply; otherwise each lane forms a 64-bit address.
+template <bool BUF>
+struct RowGather;
+
+template <>
+struct RowGather<true> {
+    __amdgpu_buffer_rsrc_t rs;
+    int voff, stride;
+    __device__ RowGather(const float *other, int nf, int lane)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(other), (short)0, 0x7FFFFFFF, 0x00020000)),
+          voff(4 * min(lane, nf - 1)), stride(4 * nf) {}
+    __device__ __forceinline__ int bits(int col) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, col * stride, 0);
+    }
+};
+
+template <>
+struct RowGather<false> {
+    const float *p;
+    int stride;
+    __device__ RowGather(const float *other, int nf, int lane) : p(other + min(lane, nf - 1)), stride(nf) {}
+    __device__ __forceinline__ int bits(int col) const { return __float_as_int(p[(size_t)col * stride]); }
+};
+
+// Wave w's chunks of 64 positions (w*64, w*64 + HS_WAVES*64, ...): the next
+// chunk's column indices load while the current chunk is gathered.  f(colv,
+// c0, m): lane j of colv holds the column of position c0 + j (0 past m).
+template <class F>
+__device__ __forceinline__ void for_chunks(const int32_t *idx, int64_t beg, int n, int w, int lane, F &&f) {
+    int c0 = w * 64;
+    if (c0 >= n) return;
+    int colv = lane < n - c0 ? idx[beg + c0 + lane] : 0;
+    for (;;) {
+        const int c1 = c0 + HS_WAVES * 64;
+        int next = 0;
+        if (c1 < n) next = lane < n - c1 ? idx[beg + c1 + lane] : 0;
+        f(colv, c0, min(64, n - c0));
+        if (c1 >= n) break;
+        colv = next;
+        c0 = c1;
+    }
+}
+
+// One chunk: HS_BATCH gathers in flight, then g(bits, j) for each position
+// j < m of the batch, in order.  The bound is uniform: full chunks run without
+// tests, and in the last chunk positions past m gather column 0 (a valid row)
+// and are skipped.
+template <bool BUF, class G>
+__device__ __forceinline__ void gather_chunk(const RowGather<BUF> &R, int colv, int m, G &&g) {
+    if (m == 64) {
+#pragma unroll 1
+        for (int j0 = 0; j0 < 64; j0 += HS_BATCH) {
+            int b[HS_BATCH];
+#pragma unroll
+            for (int j = 0; j < HS_BATCH; ++j) b[j] = R.bits(__builtin_amdgcn_readlane(colv, j0 + j));
+#pragma unroll
+            for (int j = 0; j < HS_BATCH; ++j) g(b[j], j0 + j);
+        }
+    } else {
+#pragma unroll 1
+        for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
+            int b[HS_BATCH];
+#pragma unroll
+            for (int j = 0; j < HS_BATCH; ++j) b[j] = R.bits(__builtin_amdgcn_readlane(colv, (j0 + j) & 63));
+#pragma unroll
+            for (int j = 0; j < HS_BATCH; ++j)
+                if (j0 + j < m) g(b[j], j0 + j);
+        }
+    }
 }
 
 // One counting pass over the row: for keys whose bits above `shift` equal the
-// column's prefix, count digit d = bits [shift, shift + width) if d lies in
-// [dlo, dhi).  Waves take interleaved chunks of 64 positions; lane a reads
-// column a (one 256-byte factor row per load instruction).
-template <bool WIDE, bool FIRST>
-__device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const float *other, int nf,
-                                                int64_t beg, int n, int shift, int width, int hmask, int dlo,
-                                                int dhi, int w, int lane) {
+// column's prefix, count digit d = bits [shift, shift + width).  Narrow rows:
+// bins 2j, 2j+1 share word j as two 16-bit counters (the increment is 1 or
+// 1 << 16 by the digit's low bit).  Wide rows count only d in [dlo, dhi).
+// Columns already resolved count too, into their own words, which no pick
+// reads again.
+template <bool WIDE, bool FIRST, int WIDTH, bool BUF>
+__device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const RowGather<BUF> &R,
+                                                int64_t beg, int n, int shift, int hmask, int dlo, int dhi, int w,
+                                                int lane) {
     const int pre = S.prefix[lane];
-    const bool act = !S.done[lane] && !S.found[lane];
-    const int dmask = (1 << width) - 1;
-    for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
-        const int m = min(64, n - c0);
-        const int colv = lane < m ? idx[beg + c0 + lane] : 0;
-        // HS_BATCH gathers in flight per batch, then their keys are counted
-        for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
-            int key[HS_BATCH];
-#pragma unroll
-            for (int j = 0; j < HS_BATCH; ++j) {
-                // positions past m read factor row colv = 0 (valid) and are dropped
-                const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
-                const int kk = heavy_key(other, col, lane, nf);
-                if constexpr (FIRST) key[j] = kk;
-                else key[j] = (j0 + j < m) ? kk : -1;
-            }
+    for_chunks(idx, beg, n, w, lane, [&](int colv, int, int m) {
+        gather_chunk(R, colv, m, [&](int b, int) {
+            const unsigned u = (unsigned)b;
             if constexpr (FIRST) {
-                // first pass of a narrow row: every column is open and every
-                // key counts, by its exponent byte (bits 30..23); a branch-free
-                // add, skipped only past the row's end (a uniform test)
-#pragma unroll
-                for (int j = 0; j < HS_BATCH; ++j) {
-                    if (j0 + j < m) {
-                        const int d = key[j] >> 23;
-                        atomicAdd(&S.hist[d >> 1][lane], 1u << ((d & 1) << 4));
-                    }
-                }
-                continue;
+                // every key counts by its exponent byte, bits 30..23; the
+                // barrier keeps each count next to its load's wait (clustered,
+                // the counts of a batch would hold twice the registers)
+                atomicAdd(&S.hist[__builtin_amdgcn_ubfe(u, 24, 7)][lane],
+                          __umul24(__builtin_amdgcn_ubfe(u, 23, 1), 0xFFFFu) + 1u);
+                __builtin_amdgcn_sched_barrier(0);
+            } else if constexpr (WIDE) {
+                const int d = (int)__builtin_amdgcn_ubfe(u, shift, WIDTH);
+                if ((b & hmask) == pre && d >= dlo && d < dhi) atomicAdd(&S.hist[d - dlo][lane], 1u);
+            } else {
+                if ((b & hmask) == pre)
+                    atomicAdd(&S.hist[__builtin_amdgcn_ubfe(u, shift + 1, WIDTH - 1)][lane],
+                              __umul24(__builtin_amdgcn_ubfe(u, shift, 1), 0xFFFFu) + 1u);
             }
-#pragma unroll
-            for (int j = 0; j < HS_BATCH; ++j) {
-                if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
-                    const int d = (key[j] >> shift) & dmask;
-                    if (d >= dlo && d < dhi) {
-                        if constexpr (WIDE) atomicAdd(&S.hist[d - dlo][lane], 1u);
-                        else atomicAdd(&S.hist[d >> 1][lane], 1u << ((d & 1) << 4));
-                    }
-                }
-            }
-        }
-    }
+        });
+    });
 }
 
 // Column a: walk digits dhi-1 .. dlo from the top; if the rem-th largest key
@@ -163,12 +213,16 @@ __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int
     }
 }
 
-__global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_t row_begin) {
+// Four workgroups per CU (the LDS allows four): at most 64 VGPRs.
+template <bool BUF>
+__global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_heavy_select(
+    HeavyArgs a, int64_t row_begin) {
     __shared__ HeavySelLds S;
     const int tid = threadIdx.x;
     const int w = wave_index();
     const int lane = tid & 63;
     const int nf = a.nf;
+    const RowGather<BUF> R(a.other, nf, lane);
     __shared__ int64_t next_t;
     int64_t t = blockIdx.x;
     for (;;) {
@@ -191,12 +245,15 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
         }
         const bool wide = n >= 65536;
         if (tid < 64) {
+            // padded columns (a >= n_f, all-zero keys) get the cut of a column
+            // of equal keys: the first s positions
+            const bool pad = tid >= nf;
             S.prefix[tid] = 0;
             S.rem[tid] = s;
-            S.done[tid] = 0;
+            S.done[tid] = pad ? 1 : 0;
             S.ccnt[tid] = 0;
             S.T[tid] = 0;
-            S.K[tid] = 0x7FFFFFFF;
+            S.K[tid] = pad ? s - 1 : 0x7FFFFFFF;
         }
         int hmask = 0;
         bool collected = false, all_done = false;
@@ -216,15 +273,16 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
                 const int dhi = wide ? (sub == 0 ? nd : nd / 2) : nd;
                 for (int q = tid; q < 128 * 64; q += HS_THREADS) (&S.hist[0][0])[q] = 0u;
                 __syncthreads();
-                if (wide)
-                    heavy_hist_pass<true, false>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
-                                                 lane);
+                if (wide && pass < 3)
+                    heavy_hist_pass<true, false, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                else if (wide)
+                    heavy_hist_pass<true, false, 7>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else if (pass == 0)
-                    heavy_hist_pass<false, true>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
-                                                 lane);
+                    heavy_hist_pass<false, true, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                else if (pass < 3)
+                    heavy_hist_pass<false, false, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else
-                    heavy_hist_pass<false, false>(S, a.idx, a.other, nf, beg, n, shift, width, hmask, dlo, dhi, w,
-                                                  lane);
+                    heavy_hist_pass<false, false, 7>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 __syncthreads();
                 if (tid < 64) heavy_pick(S, tid, shift, dlo, dhi, wide);
                 __syncthreads();
@@ -254,29 +312,17 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
         } else if (collected) {
             const int pre = S.prefix[lane];
             const bool act = !S.done[lane];
-            for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
-                const int m = min(64, n - c0);
-                const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
-                for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
-                    int key[HS_BATCH];
-#pragma unroll
-                    for (int j = 0; j < HS_BATCH; ++j) {
-                        const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
-                        const int kk = heavy_key(a.other, col, lane, nf);
-                        key[j] = (j0 + j < m) ? kk : -1;
-                    }
-#pragma unroll
-                    for (int j = 0; j < HS_BATCH; ++j) {
-                        if (act && key[j] >= 0 && (key[j] & hmask) == pre) {
-                            const int slot = atomicAdd(&S.ccnt[lane], 1);
-                            if (slot < HEAVY_CAP) {
-                                S.ckey[lane][slot] = key[j];
-                                S.cpos[lane][slot] = c0 + j0 + j;
-                            }
+            for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
+                gather_chunk(R, colv, m, [&](int b, int j) {
+                    if (act && (b & hmask) == pre) {
+                        const int slot = atomicAdd(&S.ccnt[lane], 1);
+                        if (slot < HEAVY_CAP) {
+                            S.ckey[lane][slot] = b & KEYMASK;
+                            S.cpos[lane][slot] = c0 + j;
                         }
                     }
-                }
-            }
+                });
+            });
             __syncthreads();
             // candidate x of column c is ranked by thread (c, x); exactly one
             // candidate per column has the wanted rank, so T and K get one writer
@@ -314,26 +360,14 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
             __syncthreads();
             if (S.flag) {
                 const int T = S.T[lane];
-                for (int c0 = w * 64; c0 < n; c0 += HS_WAVES * 64) {
-                    const int m = min(64, n - c0);
-                    const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
-                    for (int j0 = 0; j0 < m; j0 += HS_BATCH) {
-                        int key[HS_BATCH];
-#pragma unroll
-                        for (int j = 0; j < HS_BATCH; ++j) {
-                            const int col = __builtin_amdgcn_readlane(colv, (j0 + j) & 63);
-                            const int kk = heavy_key(a.other, col, lane, nf);
-                            key[j] = (j0 + j < m) ? kk : -1;
+                for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
+                    gather_chunk(R, colv, m, [&](int b, int j) {
+                        if (tie && (b & KEYMASK) == T) {
+                            const int slot = atomicAdd(&S.ccnt[lane], 1);
+                            if (slot < HEAVY_CAP) S.cpos[lane][slot] = c0 + j;
                         }
-#pragma unroll
-                        for (int j = 0; j < HS_BATCH; ++j) {
-                            if (tie && key[j] == T) {
-                                const int slot = atomicAdd(&S.ccnt[lane], 1);
-                                if (slot < HEAVY_CAP) S.cpos[lane][slot] = c0 + j0 + j;
-                            }
-                        }
-                    }
-                }
+                    });
+                });
                 __syncthreads();
                 for (int q = tid; q < 64 * HEAVY_CAP; q += HS_THREADS) {
                     const int c = q & 63, x = q >> 6;
@@ -356,8 +390,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_heavy_select(HeavyArgs a, int64_
                             const int m = min(64, n - c0);
                             const int colv = lane < m ? a.idx[beg + c0 + lane] : 0;
                             for (int j = 0; j < m; ++j) {
-                                const int col = __builtin_amdgcn_readlane(colv, j);
-                                const int key = heavy_key(a.other, col, lane, nf);
+                                const int key = R.bits(__builtin_amdgcn_readlane(colv, j)) & KEYMASK;
                                 if (over && key == T) {
                                     ++cnt;
                                     if (cnt == need) K = c0 + j;
@@ -762,7 +795,14 @@ hipError_t launch_heavy_check_reduce(const HeavyArgs &a, int64_t slot_begin, int
 
 hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_heavy_select, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a, row_begin);
+    // buffer loads address the factor matrix with 32-bit offsets
+    const bool buf = a.other_rows > 0 && a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
+    if (buf)
+        hipLaunchKernelGGL(k_heavy_select<true>, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a,
+                           row_begin);
+    else
+        hipLaunchKernelGGL(k_heavy_select<false>, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a,
+                           row_begin);
     return hipGetLastError();
 }
 

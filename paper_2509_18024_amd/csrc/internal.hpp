@@ -135,6 +135,7 @@ struct HeavyArgs {
     const int32_t *idx;
     const float *val;
     const float *other;
+    int64_t other_rows;       // rows of `other` (0: unknown)
     float *out;
     const int32_t *rows;      // heavy slot -> row (nullptr: row_begin + slot)
     int64_t count;            // heavy rows
