@@ -45,6 +45,7 @@ struct Layout {
     double *obj_out;
     float *partials;
     double *resid;
+    uint16_t *key16;
     struct SideArrays {
         int32_t *pair_slot, *pair_chunk, *cutT, *cutK;
         int64_t *pair_off;
@@ -97,6 +98,10 @@ Layout carve(const als_problem &p, void *base) {
     L.obj_out = c.take<double>(4);
     L.partials = c.take<float>((size_t)pair_cap_of(p) * (NF + 1) * 64);
     L.resid = c.take<double>((size_t)pair_cap_of(p) * 128);
+    // core-elements runs: top 16 bits of each |x| of the fixed factor
+    // matrix, read by the first two selection passes
+    const int64_t other_max = uo ? p.n_m : std::max(p.n_u, p.n_m);
+    L.key16 = c.take<uint16_t>(p.budget_num < p.budget_den ? (size_t)other_max * p.n_f : 0);
     for (int sd = 0; sd < 2; ++sd) {
         const int64_t nr = sd == 0 ? p.n_u : (uo ? 0 : p.n_m);
         const int64_t hb = heavy_bound(p, nr), pb = nr ? pair_bound(p, nr) : 0;
@@ -223,9 +228,14 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.path = nullptr;
         h.rho = nullptr;
         if (c->p.budget_num < c->p.budget_den) {
+            if (c->key16) {
+                HIP_CHECK(c, launch_key16(other, h.other_rows * h.nf, c->key16, c->stream));
+                h.key16 = c->key16;
+            }
             als_ctx::Mark mk{};
             HIP_CHECK(c, mark_begin(PROF_HSELECT, mk));
             HIP_CHECK(c, launch_heavy_select(h, 0, c->stream));
+            h.key16 = nullptr;
             HIP_CHECK(c, mark_end(mk));
         }
         for (const auto &b : H.batches) {
@@ -367,6 +377,7 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->obj_out = L.obj_out;
     c->partials = L.partials;
     c->resid = L.resid;
+    c->key16 = p->budget_num < p->budget_den ? L.key16 : nullptr;
     c->bf16 = p->precision != ALS_PREC_FP32;
     c->fp64res = p->precision == ALS_PREC_BF16_IR_FP64RES || (p->precision == ALS_PREC_AUTO && p->lambda < 1e-3);
     c->heavy_n = heavy_n_of(*p);

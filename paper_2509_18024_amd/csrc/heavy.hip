@@ -101,6 +101,19 @@ struct RowGather<false> {
     __device__ __forceinline__ int bits(int col) const { return __float_as_int(p[(size_t)col * stride]); }
 };
 
+// The same gathers from the 16-bit key copy (bits 30..15 of each entry, the
+// digits of the first two passes): half the bytes of a factor row.
+struct KeyGather16 {
+    __amdgpu_buffer_rsrc_t rs;
+    int voff, stride;
+    __device__ KeyGather16(const uint16_t *key16, int nf, int lane)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(key16), (short)0, 0x7FFFFFFF, 0x00020000)),
+          voff(2 * min(lane, nf - 1)), stride(2 * nf) {}
+    __device__ __forceinline__ int bits(int col) const {
+        return (int)__builtin_amdgcn_raw_buffer_load_b16(rs, voff, col * stride, 0);
+    }
+};
+
 // Wave w's chunks of 64 positions (w*64, w*64 + HS_WAVES*64, ...): the next
 // chunk's column indices load while the current chunk is gathered.  f(colv,
 // c0, m): lane j of colv holds the column of position c0 + j (0 past m).
@@ -124,8 +137,8 @@ __device__ __forceinline__ void for_chunks(const int32_t *idx, int64_t beg, int 
 // j < m of the batch, in order.  The bound is uniform: full chunks run without
 // tests, and in the last chunk positions past m gather column 0 (a valid row)
 // and are skipped.
-template <bool BUF, class G>
-__device__ __forceinline__ void gather_chunk(const RowGather<BUF> &R, int colv, int m, G &&g) {
+template <class RG, class G>
+__device__ __forceinline__ void gather_chunk(const RG &R, int colv, int m, G &&g) {
     if (m == 64) {
 #pragma unroll 1
         for (int j0 = 0; j0 < 64; j0 += HS_BATCH) {
@@ -153,12 +166,12 @@ __device__ __forceinline__ void gather_chunk(const RowGather<BUF> &R, int colv, 
 // bins 2j, 2j+1 share word j as two 16-bit counters (the increment is 1 or
 // 1 << 16 by the digit's low bit).  Wide rows count only d in [dlo, dhi).
 // Columns already resolved count too, into their own words, which no pick
-// reads again.
-template <bool WIDE, bool FIRST, int WIDTH, bool BUF>
-__device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const RowGather<BUF> &R,
-                                                int64_t beg, int n, int shift, int hmask, int dlo, int dhi, int w,
-                                                int lane) {
-    const int pre = S.prefix[lane];
+// reads again.  The gathered values hold key bits KOFF.. (shift and hmask are
+// given in those units; KOFF = 15 for the 16-bit key copy).
+template <bool WIDE, bool FIRST, int WIDTH, int KOFF, class RG>
+__device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *idx, const RG &R, int64_t beg,
+                                                int n, int shift, int hmask, int dlo, int dhi, int w, int lane) {
+    const int pre = S.prefix[lane] >> KOFF;
     for_chunks(idx, beg, n, w, lane, [&](int colv, int, int m) {
         gather_chunk(R, colv, m, [&](int b, int) {
             const unsigned u = (unsigned)b;
@@ -166,8 +179,8 @@ __device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *i
                 // every key counts by its exponent byte, bits 30..23; the
                 // barrier keeps each count next to its load's wait (clustered,
                 // the counts of a batch would hold twice the registers)
-                atomicAdd(&S.hist[__builtin_amdgcn_ubfe(u, 24, 7)][lane],
-                          __umul24(__builtin_amdgcn_ubfe(u, 23, 1), 0xFFFFu) + 1u);
+                atomicAdd(&S.hist[__builtin_amdgcn_ubfe(u, 24 - KOFF, 7)][lane],
+                          __umul24(__builtin_amdgcn_ubfe(u, 23 - KOFF, 1), 0xFFFFu) + 1u);
                 __builtin_amdgcn_sched_barrier(0);
             } else if constexpr (WIDE) {
                 const int d = (int)__builtin_amdgcn_ubfe(u, shift, WIDTH);
@@ -213,8 +226,9 @@ __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int
     }
 }
 
-// Four workgroups per CU (the LDS allows four): at most 64 VGPRs.
-template <bool BUF>
+// Four workgroups per CU (the LDS allows four): at most 64 VGPRs.  K16: the
+// first two passes read the 16-bit key copy.
+template <bool BUF, bool K16>
 __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_heavy_select(
     HeavyArgs a, int64_t row_begin) {
     __shared__ HeavySelLds S;
@@ -223,6 +237,7 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const int lane = tid & 63;
     const int nf = a.nf;
     const RowGather<BUF> R(a.other, nf, lane);
+    const KeyGather16 R16(a.key16, nf, lane);
     __shared__ int64_t next_t;
     int64_t t = blockIdx.x;
     for (;;) {
@@ -273,16 +288,25 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                 const int dhi = wide ? (sub == 0 ? nd : nd / 2) : nd;
                 for (int q = tid; q < 128 * 64; q += HS_THREADS) (&S.hist[0][0])[q] = 0u;
                 __syncthreads();
-                if (wide && pass < 3)
-                    heavy_hist_pass<true, false, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                if (K16 && pass < 2) {
+                    // the digits of the first two passes lie in bits 30..15
+                    const int sh = shift - 15, hm = hmask >> 15;
+                    if (wide)
+                        heavy_hist_pass<true, false, 8, 15>(S, a.idx, R16, beg, n, sh, hm, dlo, dhi, w, lane);
+                    else if (pass == 0)
+                        heavy_hist_pass<false, true, 8, 15>(S, a.idx, R16, beg, n, sh, hm, dlo, dhi, w, lane);
+                    else
+                        heavy_hist_pass<false, false, 8, 15>(S, a.idx, R16, beg, n, sh, hm, dlo, dhi, w, lane);
+                } else if (wide && pass < 3)
+                    heavy_hist_pass<true, false, 8, 0>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else if (wide)
-                    heavy_hist_pass<true, false, 7>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                    heavy_hist_pass<true, false, 7, 0>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else if (pass == 0)
-                    heavy_hist_pass<false, true, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                    heavy_hist_pass<false, true, 8, 0>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else if (pass < 3)
-                    heavy_hist_pass<false, false, 8>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                    heavy_hist_pass<false, false, 8, 0>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 else
-                    heavy_hist_pass<false, false, 7>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
+                    heavy_hist_pass<false, false, 7, 0>(S, a.idx, R, beg, n, shift, hmask, dlo, dhi, w, lane);
                 __syncthreads();
                 if (tid < 64) heavy_pick(S, tid, shift, dlo, dhi, wide);
                 __syncthreads();
@@ -310,8 +334,8 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         if (all_done) {
             // every cut was fixed by a prefix alone
         } else if (collected) {
-            const int pre = S.prefix[lane];
             const bool act = !S.done[lane];
+            const int pre = S.prefix[lane];
             for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
                 gather_chunk(R, colv, m, [&](int b, int j) {
                     if (act && (b & hmask) == pre) {
@@ -793,16 +817,49 @@ hipError_t launch_heavy_check_reduce(const HeavyArgs &a, int64_t slot_begin, int
     return hipGetLastError();
 }
 
+// key16[i] = bits 30..15 of other[i] (exponent and top mantissa byte of |x|);
+// eight entries per thread, 16-byte accesses when `other` is 16-byte aligned.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_key16(const float *other, int64_t count, uint16_t *key16) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * 8;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; i < count; i += step) {
+        if (VEC && i + 8 <= count) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(other + i);
+            const uint4 y = *reinterpret_cast<const uint4 *>(other + i + 4);
+            uint4 o;
+            o.x = ((x.x >> 15) & 0xFFFFu) | (((x.y >> 15) & 0xFFFFu) << 16);
+            o.y = ((x.z >> 15) & 0xFFFFu) | (((x.w >> 15) & 0xFFFFu) << 16);
+            o.z = ((y.x >> 15) & 0xFFFFu) | (((y.y >> 15) & 0xFFFFu) << 16);
+            o.w = ((y.z >> 15) & 0xFFFFu) | (((y.w >> 15) & 0xFFFFu) << 16);
+            *reinterpret_cast<uint4 *>(key16 + i) = o;
+        } else {
+            for (int64_t k = i; k < i + 8 && k < count; ++k)
+                key16[k] = (uint16_t)((__float_as_uint(other[k]) >> 15) & 0xFFFFu);
+        }
+    }
+}
+
+hipError_t launch_key16(const float *other, int64_t count, uint16_t *key16, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 2047) / 2048, 16384);
+    if ((reinterpret_cast<uintptr_t>(other) & 15) == 0 && (reinterpret_cast<uintptr_t>(key16) & 15) == 0)
+        hipLaunchKernelGGL(k_key16<true>, dim3(blocks), dim3(256), 0, s, other, count, key16);
+    else
+        hipLaunchKernelGGL(k_key16<false>, dim3(blocks), dim3(256), 0, s, other, count, key16);
+    return hipGetLastError();
+}
+
 hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;
     // buffer loads address the factor matrix with 32-bit offsets
     const bool buf = a.other_rows > 0 && a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
-    if (buf)
-        hipLaunchKernelGGL(k_heavy_select<true>, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a,
-                           row_begin);
+    const dim3 grid(blocks_for(a.count, 1, 8192));
+    if (buf && a.key16)
+        hipLaunchKernelGGL((k_heavy_select<true, true>), grid, dim3(HS_THREADS), 0, s, a, row_begin);
+    else if (buf)
+        hipLaunchKernelGGL((k_heavy_select<true, false>), grid, dim3(HS_THREADS), 0, s, a, row_begin);
     else
-        hipLaunchKernelGGL(k_heavy_select<false>, dim3(blocks_for(a.count, 1, 8192)), dim3(HS_THREADS), 0, s, a,
-                           row_begin);
+        hipLaunchKernelGGL((k_heavy_select<false, false>), grid, dim3(HS_THREADS), 0, s, a, row_begin);
     return hipGetLastError();
 }
 

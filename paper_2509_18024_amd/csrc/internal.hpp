@@ -136,6 +136,7 @@ struct HeavyArgs {
     const float *val;
     const float *other;
     int64_t other_rows;       // rows of `other` (0: unknown)
+    const uint16_t *key16;    // bits 30..15 of `other`'s entries, or nullptr (selection)
     float *out;
     const int32_t *rows;      // heavy slot -> row (nullptr: row_begin + slot)
     int64_t count;            // heavy rows
@@ -195,6 +196,7 @@ hipError_t launch_check_class(int cls, const SweepArgs &a, int max_blocks, hipSt
 
 // launchers (heavy.hip)
 hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_t s);
+hipError_t launch_key16(const float *other, int64_t count, uint16_t *key16, hipStream_t s);
 hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 hipError_t launch_heavy_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
                               hipStream_t s);
@@ -242,6 +244,7 @@ struct als_ctx {
     double *obj_out = nullptr;            // [4]
     float *partials = nullptr;            // [pair_cap * (NF + 1) * 64]
     double *resid = nullptr;              // [pair_cap * 128]
+    uint16_t *key16 = nullptr;            // [max(n_u, n_m) * n_f] when budget < 1
     int32_t heavy_n = coreals::DEFAULT_HEAVY_N;
     int32_t chunk = coreals::DEFAULT_CHUNK;
     int64_t pair_cap = coreals::PAIR_CAP;
