@@ -91,6 +91,10 @@ struct RowGather<true> {
     __device__ __forceinline__ int bits(int col) const {
         return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, col * stride, 0);
     }
+    // a different row per lane
+    __device__ __forceinline__ int bits_lane(int col) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, voff + col * stride, 0, 0);
+    }
 };
 
 template <>
@@ -227,7 +231,7 @@ __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int
 }
 
 // Four workgroups per CU (the LDS allows four): at most 64 VGPRs.  K16: the
-// first two passes read the 16-bit key copy.
+// first two passes and the candidate collection read the 16-bit key copy.
 template <bool BUF, bool K16>
 __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_heavy_select(
     HeavyArgs a, int64_t row_begin) {
@@ -335,18 +339,40 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
             // every cut was fixed by a prefix alone
         } else if (collected) {
             const bool act = !S.done[lane];
-            const int pre = S.prefix[lane];
-            for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
-                gather_chunk(R, colv, m, [&](int b, int j) {
-                    if (act && (b & hmask) == pre) {
-                        const int slot = atomicAdd(&S.ccnt[lane], 1);
-                        if (slot < HEAVY_CAP) {
-                            S.ckey[lane][slot] = b & KEYMASK;
-                            S.cpos[lane][slot] = c0 + j;
+            if constexpr (K16 && BUF) {
+                // candidates share the 16-bit key: note their positions and
+                // columns, then fetch their full keys (about n / 1000 per
+                // column, so mostly one load per thread)
+                const int pre16 = S.prefix[lane] >> 15;
+                for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
+                    gather_chunk(R16, colv, m, [&](int b, int j) {
+                        if (act && b == pre16) {
+                            const int slot = atomicAdd(&S.ccnt[lane], 1);
+                            if (slot < HEAVY_CAP) {
+                                S.ckey[lane][slot] = __builtin_amdgcn_readlane(colv, j);
+                                S.cpos[lane][slot] = c0 + j;
+                            }
                         }
-                    }
+                    });
                 });
-            });
+                __syncthreads();
+                const int mc = act ? min(S.ccnt[lane], HEAVY_CAP) : 0;
+#pragma unroll 1
+                for (int x = w; x < mc; x += HS_WAVES) S.ckey[lane][x] = R.bits_lane(S.ckey[lane][x]) & KEYMASK;
+            } else {
+                const int pre = S.prefix[lane];
+                for_chunks(a.idx, beg, n, w, lane, [&](int colv, int c0, int m) {
+                    gather_chunk(R, colv, m, [&](int b, int j) {
+                        if (act && (b & hmask) == pre) {
+                            const int slot = atomicAdd(&S.ccnt[lane], 1);
+                            if (slot < HEAVY_CAP) {
+                                S.ckey[lane][slot] = b & KEYMASK;
+                                S.cpos[lane][slot] = c0 + j;
+                            }
+                        }
+                    });
+                });
+            }
             __syncthreads();
             // candidate x of column c is ranked by thread (c, x); exactly one
             // candidate per column has the wanted rank, so T and K get one writer
