@@ -317,7 +317,7 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
 
 # HIP kernel behind each timed group (group 8 is k_heavy_gram_bf16 in the BF16 modes)
 KERNEL_OF_GROUP = ["k_sweep_full"] + [f"k_sweep_core<{c}>" for c in range(1, 7)] + [
-    "k_heavy_select", "k_heavy_gram", "k_heavy_solve", "k_heavy_resid", "k_heavy_refine"]
+    "k_heavy_select", "k_heavy_gram_f32", "k_heavy_solve", "k_heavy_resid", "k_heavy_refine"]
 
 TRAFFIC_FILE = os.path.join(ROOT, "paper_2509_18024_amd", "tuning", "hbm_traffic_gfx950.json")
 
@@ -394,14 +394,14 @@ def main():
     prob = synth.c3_batched(scale=args.scale)
     log(f"generated n_u={prob.n_u} n_m={prob.n_m} nnz={prob.nnz} in {time.time() - t:.1f}s")
 
-    # headline: core-elements ALS, r = 1/10, BF16 Gram + refinement (heavy rows);
-    # comparator: plain full-data ALS in FP32 on the same GPU
+    # headline: core-elements ALS, r = 1/10, FP32 throughout (heavy-row Gram on
+    # FP32 MFMA tiles); comparator: plain full-data ALS in FP32 on the same GPU
     from paper_2509_18024_amd import autotune
-    HEAD = "core_r1/10_bf16ir"
-    variants = [(HEAD, (1, 10), 1)]
+    HEAD = "core_r1/10_fp32"
+    variants = [(HEAD, (1, 10), 0)]
     if not args.headline_only:
-        variants += [("core_r1/10_fp32", (1, 10), 0), ("core_r1/20_bf16ir", (1, 20), 1),
-                     ("core_r1/4_bf16ir", (1, 4), 1), ("full_fp32", (1, 1), 0),
+        variants += [("core_r1/10_bf16ir", (1, 10), 1), ("core_r1/20_fp32", (1, 20), 0),
+                     ("core_r1/4_fp32", (1, 4), 0), ("full_fp32", (1, 1), 0),
                      ("full_bf16ir", (1, 1), 1)]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -412,7 +412,7 @@ def main():
     # coordinate search on the box (written to gpurun_out/ for review)
     tune_out = os.path.join(ROOT, "gpurun_out", "tuning_gfx950.json")
     schedules = {}
-    for key, b, prec in [("core", (1, 10), 1), ("full", (1, 1), 0)]:
+    for key, b, prec in [("core", (1, 10), 0), ("full", (1, 1), 0)]:
         if args.no_tune:
             schedules[key] = dict(autotune.DEFAULT)
             continue
@@ -514,13 +514,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"c3_batched: n_u={prob.n_u}, n_m={prob.n_m}, n_f={prob.n_f}, "
                          f"nnz={prob.nnz}, user degree 1+Lomax(1.5) capped 50k, item popularity "
                          f"Zipf(1.1) water-filled at 50k, lambda={prob.lam}, core-elements r=1/10, "
-                         f"BF16 MFMA Gram + one refinement step on heavy rows, FP32 elsewhere; "
+                         f"FP32 throughout (heavy-row Gram on FP32 MFMA tiles); "
                          f"step = users + items half-sweep"),
             "parallelism": "single GPU",
         },

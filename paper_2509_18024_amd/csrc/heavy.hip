@@ -1,25 +1,28 @@
 // Heavy rows of a half-sweep (gfx950): rows whose budget exceeds the register
 // insertion networks (s > 32) or whose degree exceeds the light-row limit.
 //
-//   k_heavy_select  one 256-thread workgroup per row computes the CES cut of
-//                   all 64 columns (Algorithm 1): an MSD radix select on the
-//                   31-bit key |x|, 8 bits per pass, with per-column counters
-//                   packed two per 32-bit LDS word (degrees < 65536).  After two
-//                   passes (exponent byte, top mantissa byte) the few keys that
-//                   share the threshold's 16-bit prefix are copied into LDS and
-//                   ranked exactly by (key desc, position asc); only if more
-//                   than HEAVY_CAP keys share it do two more radix passes, and
-//                   a position pass where keys equal the threshold.  Three
-//                   gathers of the row in the common case.
-//   k_heavy_gram    one wavefront per (row, chunk of `chunk` entries) builds
-//                   the chunk's part of X*^T X and X*^T y (eq. core_ui) with
-//                   the row's cut, and stores it to scratch (column-major, so
-//                   lane a writes row a of the system with coalesced stores).
-//   k_heavy_solve   one wavefront per row sums its partial systems in chunk
-//                   order (deterministic), adds lambda n_i, and solves it
-//                   (pivoted LU).
+//   k_key16          the top 16 bits of every |x| of the fixed factor matrix
+//                    (exponent and first mantissa byte), half the bytes of a
+//                    factor row, for the selection's first two passes.
+//   k_heavy_select   one 512-thread workgroup per row computes the CES cut of
+//                    all 64 columns (Algorithm 1): an MSD radix select on the
+//                    31-bit key |x|, 8 bits per pass, with per-column counters
+//                    packed two per 32-bit LDS word (degrees < 65536).  After
+//                    two passes (exponent byte, top mantissa byte) the few keys
+//                    that share the threshold's 16-bit prefix are collected
+//                    into LDS and ranked exactly by (key desc, position asc);
+//                    only if more than HEAVY_CAP keys share it do two more
+//                    radix passes over the full keys run, and a position pass
+//                    where keys equal the threshold.
+//   k_heavy_gram_f32 one wavefront per (row, chunk of `chunk` entries) builds
+//                    the chunk's part of X*^T X and X*^T y (eq. core_ui) with
+//                    the row's cut on 32x32x2 FP32 MFMA tiles, and stores it
+//                    to scratch (column-major: element (a, b) at b * 64 + a).
+//   k_heavy_solve    one wavefront per row sums its partial systems in chunk
+//                    order (deterministic), adds lambda n_i, and solves it
+//                    (pivoted LU).
 //
-// BF16 precision modes replace k_heavy_gram by k_heavy_gram_bf16 (the same
+// BF16 precision modes replace k_heavy_gram_f32 by k_heavy_gram_bf16 (the same
 // partial systems from bf16 MFMA tiles with FP32 accumulation) and add one
 // step of iterative refinement: k_heavy_resid forms the partial residuals
 // X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
@@ -462,37 +465,6 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     }
 }
 
-__global__ __launch_bounds__(WPB * 64) void k_heavy_gram(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
-    __shared__ WaveLds lds[WPB];
-    const int w = wave_index();
-    const int lane = threadIdx.x & 63;
-    WaveLds &L = lds[w];
-    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
-    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
-        const int64_t slot = a.pair_slot[p];
-        const int chunk = a.pair_chunk[p];
-        const int64_t i = a.rows[slot];
-        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
-        const int64_t beg = a.ptr[i];
-        const int n = (int)(a.ptr[i + 1] - beg);
-        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
-        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
-        Cut c;
-        if (s == n) c = Cut{0, 0, false, true};
-        else if (s == 0) c = Cut{0, 0, true, false};
-        else c = Cut{a.cutT[slot * 64 + lane], a.cutK[slot * 64 + lane], false, false};
-        const int kb = chunk * a.chunk;
-        const int ke = min(n, kb + a.chunk);
-        float A[NF];
-        float rhs;
-        gram_range(L, r, c, kb, ke, lane, A, rhs);
-        float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
-#pragma unroll
-        for (int b = 0; b < NF; ++b) dst[b * 64 + lane] = A[b];
-        dst[NF * 64 + lane] = rhs;
-    }
-}
-
 __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
                                                           int64_t pair_base) {
     __shared__ WaveLds lds[WPB];
@@ -674,6 +646,96 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
         if (h == 0) {
             dst[NF * 64 + m] = racc[0];
             dst[NF * 64 + 32 + m] = racc[1];
+        }
+    }
+}
+
+// FP32 Gram of a (row, chunk) pair on 32x32x2 FP32 MFMA tiles (exact FP32
+// products, FP32 accumulation): accurate enough that no refinement step is
+// needed.  Operands come straight from memory: for entries
+// (k, k + 1) lane (m, h) loads columns m and 32 + m of factor row idx[k + h]
+// (two 128-byte segments per load instruction), which is exactly its A and B
+// operand slot; A = X*^T (masked by the row's cut), B = X.
+constexpr int GF_PAIRS = 16;  // entry pairs gathered per batch
+
+__global__ __launch_bounds__(WPB * 64) void k_heavy_gram_f32(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    const int w = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 31, h = lane >> 5;
+    const int nf = a.nf;
+    const bool live0 = m < nf, live1 = 32 + m < nf;  // padded columns hold zeros
+    const int col0 = min(m, nf - 1), col1 = min(32 + m, nf - 1);
+    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
+        const int64_t slot = a.pair_slot[p];
+        const int chunk = a.pair_chunk[p];
+        const int64_t i = a.rows[slot];
+        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
+        const int64_t beg = a.ptr[i];
+        const int n = (int)(a.ptr[i + 1] - beg);
+        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
+        Cut c0, c1;
+        if (s == n) c0 = c1 = Cut{0, 0, false, true};
+        else if (s == 0) c0 = c1 = Cut{0, 0, true, false};
+        else {
+            c0 = Cut{a.cutT[slot * 64 + m], a.cutK[slot * 64 + m], false, false};
+            c1 = Cut{a.cutT[slot * 64 + 32 + m], a.cutK[slot * 64 + 32 + m], false, false};
+        }
+        f32x16 acc00, acc01, acc10, acc11;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc00[q] = acc01[q] = acc10[q] = acc11[q] = 0.f;
+        float racc0 = 0.f, racc1 = 0.f;
+        const int kb = chunk * a.chunk;
+        const int ke = min(n, kb + a.chunk);
+        for (int k0 = kb; k0 < ke; k0 += 2 * GF_PAIRS) {
+            // lane j of colv / yv: entry k0 + j (j < 2 * GF_PAIRS), column 0 and
+            // rating 0 past the chunk
+            const int kl = k0 + (lane & (2 * GF_PAIRS - 1));
+            const bool okl = kl < ke;
+            const int colv = okl ? a.idx[beg + kl] : 0;
+            const float yv = okl ? a.val[beg + kl] : 0.f;
+            float x0[GF_PAIRS], x1[GF_PAIRS];
+#pragma unroll
+            for (int q = 0; q < GF_PAIRS; ++q) {
+                const int ce = __builtin_amdgcn_readlane(colv, 2 * q), co = __builtin_amdgcn_readlane(colv, 2 * q + 1);
+                const float *row = a.other + (size_t)(h ? co : ce) * nf;
+                x0[q] = row[col0];
+                x1[q] = row[col1];
+            }
+#pragma unroll
+            for (int q = 0; q < GF_PAIRS; ++q) {
+                const int k = k0 + 2 * q + h;
+                const bool ok = k < ke;
+                const float v0 = (ok && live0) ? x0[q] : 0.f;
+                const float v1 = (ok && live1) ? x1[q] : 0.f;
+                const float w0 = kept(c0, key_of(v0), k) ? v0 : 0.f;
+                const float w1 = kept(c1, key_of(v1), k) ? v1 : 0.f;
+                const float ye = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), 2 * q));
+                const float yo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), 2 * q + 1));
+                const float y = h ? yo : ye;
+                racc0 = fmaf(w0, y, racc0);
+                racc1 = fmaf(w1, y, racc1);
+                acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v0, acc00, 0, 0, 0);
+                acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v1, acc01, 0, 0, 0);
+                acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v0, acc10, 0, 0, 0);
+                acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v1, acc11, 0, 0, 0);
+            }
+        }
+        racc0 += __shfl_xor(racc0, 32);
+        racc1 += __shfl_xor(racc1, 32);
+        // D[i][j] of tile (ta, tb) = A[32 ta + i][32 tb + j], stored at
+        // dst[(32 tb + j) * 64 + 32 ta + i], the layout k_heavy_solve reads
+        float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int row = 8 * (q >> 2) + 4 * h + (q & 3);
+            dst[m * 64 + row] = acc00[q];
+            dst[(32 + m) * 64 + row] = acc01[q];
+            dst[m * 64 + 32 + row] = acc10[q];
+            dst[(32 + m) * 64 + 32 + row] = acc11[q];
+        }
+        if (h == 0) {
+            dst[NF * 64 + m] = racc0;
+            dst[NF * 64 + 32 + m] = racc1;
         }
     }
 }
@@ -891,8 +953,8 @@ hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_
 
 hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
     if (pair_end <= pair_begin) return hipSuccess;
-    hipLaunchKernelGGL(k_heavy_gram, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
-                       pair_begin, pair_end);
+    hipLaunchKernelGGL(k_heavy_gram_f32, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
+                       a, pair_begin, pair_end);
     return hipGetLastError();
 }
 
