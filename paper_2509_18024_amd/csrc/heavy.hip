@@ -652,19 +652,30 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
 
 // FP32 Gram of a (row, chunk) pair on 32x32x2 FP32 MFMA tiles (exact FP32
 // products, FP32 accumulation): accurate enough that no refinement step is
-// needed.  Operands come straight from memory: for entries
-// (k, k + 1) lane (m, h) loads columns m and 32 + m of factor row idx[k + h]
-// (two 128-byte segments per load instruction), which is exactly its A and B
-// operand slot; A = X*^T (masked by the row's cut), B = X.
-constexpr int GF_PAIRS = 16;  // entry pairs gathered per batch
+// needed.  Operands come straight from memory: for entries (k, k + 1) lane
+// (m, h) loads columns m and 32 + m of factor row idx[k + h] (two 128-byte
+// segments per load instruction), which is exactly its A and B operand slot;
+// A = X*^T (masked by the row's cut), B = X.  Column indices and ratings of a
+// 64-entry block are parked in LDS so that each lane reads its own with one
+// LDS load; the cut test is one 64-bit compare of (key, -position).  Entries
+// past the chunk and padded columns (a >= n_f) read zeros: their buffer
+// offsets lie beyond the factor matrix, where buffer loads return 0.
+constexpr int GF_PAIRS = 16;               // entry pairs gathered per batch
+constexpr uint32_t GF_NONE = 0x80000000u;  // an offset past any factor matrix
 
-__global__ __launch_bounds__(WPB * 64) void k_heavy_gram_f32(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_f32(
+    HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
+    __shared__ int s_col[WPB][64];
+    __shared__ float s_y[WPB][64];
     const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int m = lane & 31, h = lane >> 5;
     const int nf = a.nf;
-    const bool live0 = m < nf, live1 = 32 + m < nf;  // padded columns hold zeros
-    const int col0 = min(m, nf - 1), col1 = min(32 + m, nf - 1);
+    const uint32_t off0 = m < nf ? 4 * m : GF_NONE, off1 = 32 + m < nf ? 4 * (32 + m) : GF_NONE;
+    const int stride = 4 * nf;
+    const int rows = (int)a.other_rows;  // column `rows`: past the matrix
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(a.other), (short)0, (int)(a.other_rows * nf * 4), 0x00020000);
     for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
         const int64_t slot = a.pair_slot[p];
         const int chunk = a.pair_chunk[p];
@@ -673,51 +684,73 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_f32(HeavyArgs a, int64_
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
-        Cut c0, c1;
-        if (s == n) c0 = c1 = Cut{0, 0, false, true};
-        else if (s == 0) c0 = c1 = Cut{0, 0, true, false};
-        else {
-            c0 = Cut{a.cutT[slot * 64 + m], a.cutK[slot * 64 + m], false, false};
-            c1 = Cut{a.cutT[slot * 64 + 32 + m], a.cutK[slot * 64 + 32 + m], false, false};
+        // kept(k) <=> (key, ~k) >= (T, ~K) as unsigned 64-bit pairs; every
+        // entry is kept with (T, K) = (0, INT_MAX), none with s = 0
+        int T0 = 0, K0 = 0x7FFFFFFF, T1 = 0, K1 = 0x7FFFFFFF;
+        if (s < n) {
+            T0 = a.cutT[slot * 64 + m];
+            K0 = a.cutK[slot * 64 + m];
+            T1 = a.cutT[slot * 64 + 32 + m];
+            K1 = a.cutK[slot * 64 + 32 + m];
         }
+        if (s == 0) {
+            T0 = T1 = 0x7FFFFFFF;
+            K0 = K1 = -1;
+        }
+        const uint64_t b0 = ((uint64_t)(uint32_t)T0 << 32) | (uint32_t)~K0;
+        const uint64_t b1 = ((uint64_t)(uint32_t)T1 << 32) | (uint32_t)~K1;
         f32x16 acc00, acc01, acc10, acc11;
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc00[q] = acc01[q] = acc10[q] = acc11[q] = 0.f;
         float racc0 = 0.f, racc1 = 0.f;
         const int kb = chunk * a.chunk;
         const int ke = min(n, kb + a.chunk);
-        for (int k0 = kb; k0 < ke; k0 += 2 * GF_PAIRS) {
-            // lane j of colv / yv: entry k0 + j (j < 2 * GF_PAIRS), column 0 and
-            // rating 0 past the chunk
-            const int kl = k0 + (lane & (2 * GF_PAIRS - 1));
-            const bool okl = kl < ke;
-            const int colv = okl ? a.idx[beg + kl] : 0;
-            const float yv = okl ? a.val[beg + kl] : 0.f;
-            float x0[GF_PAIRS], x1[GF_PAIRS];
-#pragma unroll
-            for (int q = 0; q < GF_PAIRS; ++q) {
-                const int ce = __builtin_amdgcn_readlane(colv, 2 * q), co = __builtin_amdgcn_readlane(colv, 2 * q + 1);
-                const float *row = a.other + (size_t)(h ? co : ce) * nf;
-                x0[q] = row[col0];
-                x1[q] = row[col1];
+        // lane j of colv / yv: entry k0 + j of the block, column `rows` and
+        // rating 0 past the chunk; the next block's load while this one is used
+        int colv = kb + lane < ke ? a.idx[beg + kb + lane] : rows;
+        float yv = kb + lane < ke ? a.val[beg + kb + lane] : 0.f;
+        for (int k0 = kb; k0 < ke; k0 += 64) {
+            wave_sync();  // the previous block's LDS reads are done
+            s_col[w][lane] = colv;
+            s_y[w][lane] = yv;
+            wave_sync();
+            const int k1 = k0 + 64;
+            colv = rows;
+            yv = 0.f;
+            if (k1 < ke) {
+                colv = k1 + lane < ke ? a.idx[beg + k1 + lane] : rows;
+                yv = k1 + lane < ke ? a.val[beg + k1 + lane] : 0.f;
             }
+#pragma unroll 1
+            for (int e0 = k0; e0 < min(ke, k1); e0 += 2 * GF_PAIRS) {
+                const int j0 = e0 - k0;
+                float x0[GF_PAIRS], x1[GF_PAIRS], yq[GF_PAIRS];
 #pragma unroll
-            for (int q = 0; q < GF_PAIRS; ++q) {
-                const int k = k0 + 2 * q + h;
-                const bool ok = k < ke;
-                const float v0 = (ok && live0) ? x0[q] : 0.f;
-                const float v1 = (ok && live1) ? x1[q] : 0.f;
-                const float w0 = kept(c0, key_of(v0), k) ? v0 : 0.f;
-                const float w1 = kept(c1, key_of(v1), k) ? v1 : 0.f;
-                const float ye = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), 2 * q));
-                const float yo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), 2 * q + 1));
-                const float y = h ? yo : ye;
-                racc0 = fmaf(w0, y, racc0);
-                racc1 = fmaf(w1, y, racc1);
-                acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v0, acc00, 0, 0, 0);
-                acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v1, acc01, 0, 0, 0);
-                acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v0, acc10, 0, 0, 0);
-                acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v1, acc11, 0, 0, 0);
+                for (int q = 0; q < GF_PAIRS; ++q) {
+                    const int col = s_col[w][j0 + 2 * q + h];
+                    yq[q] = s_y[w][j0 + 2 * q + h];
+                    const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
+                    x0[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
+                    x1[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
+                }
+                // every gather of the batch is issued before the first use
+                __builtin_amdgcn_sched_barrier(0);
+                const uint32_t nk0 = ~(uint32_t)(e0 + h);  // ~k of pair 0
+#pragma unroll
+                for (int q = 0; q < GF_PAIRS; ++q) {
+                    const float v0 = x0[q], v1 = x1[q];
+                    const uint32_t nk = nk0 - 2u * q;
+                    const uint64_t a0 = ((uint64_t)(__float_as_uint(v0) & 0x7FFFFFFFu) << 32) | nk;
+                    const uint64_t a1 = ((uint64_t)(__float_as_uint(v1) & 0x7FFFFFFFu) << 32) | nk;
+                    const float w0 = a0 >= b0 ? v0 : 0.f;
+                    const float w1 = a1 >= b1 ? v1 : 0.f;
+                    racc0 = fmaf(w0, yq[q], racc0);
+                    racc1 = fmaf(w1, yq[q], racc1);
+                    acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v0, acc00, 0, 0, 0);
+                    acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v1, acc01, 0, 0, 0);
+                    acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v0, acc10, 0, 0, 0);
+                    acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v1, acc11, 0, 0, 0);
+                }
             }
         }
         racc0 += __shfl_xor(racc0, 32);
@@ -953,6 +986,9 @@ hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_
 
 hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
     if (pair_end <= pair_begin) return hipSuccess;
+    // buffer offsets are 24-bit products row * 4 n_f plus 32-bit sums
+    if (a.other_rows <= 0 || a.other_rows >= (1 << 24) || a.other_rows * (int64_t)a.nf * 4 > (int64_t)0x7FFFFFFF)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_heavy_gram_f32, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
                        a, pair_begin, pair_end);
     return hipGetLastError();
