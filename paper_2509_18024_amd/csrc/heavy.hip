@@ -663,7 +663,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
 constexpr int GF_PAIRS = 16;               // entry pairs gathered per batch
 constexpr uint32_t GF_NONE = 0x80000000u;  // an offset past any factor matrix
 
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_f32(
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_heavy_gram_f32(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
     __shared__ float s_y[WPB][64];
@@ -724,11 +724,10 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
 #pragma unroll 1
             for (int e0 = k0; e0 < min(ke, k1); e0 += 2 * GF_PAIRS) {
                 const int j0 = e0 - k0;
-                float x0[GF_PAIRS], x1[GF_PAIRS], yq[GF_PAIRS];
+                float x0[GF_PAIRS], x1[GF_PAIRS];
 #pragma unroll
                 for (int q = 0; q < GF_PAIRS; ++q) {
                     const int col = s_col[w][j0 + 2 * q + h];
-                    yq[q] = s_y[w][j0 + 2 * q + h];
                     const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
                     x0[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
                     x1[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
@@ -744,8 +743,9 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                     const uint64_t a1 = ((uint64_t)(__float_as_uint(v1) & 0x7FFFFFFFu) << 32) | nk;
                     const float w0 = a0 >= b0 ? v0 : 0.f;
                     const float w1 = a1 >= b1 ? v1 : 0.f;
-                    racc0 = fmaf(w0, yq[q], racc0);
-                    racc1 = fmaf(w1, yq[q], racc1);
+                    const float y = s_y[w][j0 + 2 * q + h];
+                    racc0 = fmaf(w0, y, racc0);
+                    racc1 = fmaf(w1, y, racc1);
                     acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v0, acc00, 0, 0, 0);
                     acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v1, acc01, 0, 0, 0);
                     acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v0, acc10, 0, 0, 0);
