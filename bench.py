@@ -342,9 +342,9 @@ def measured_traffic(kernel: str):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("source_sha256") != kernel_source_digest() or t.get("kernel") != kernel:
+    if t.get("source_sha256") != kernel_source_digest() or kernel not in t.get("kernels", {}):
         return None
-    return t["hbm_bytes_per_launch"]
+    return t["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=3):
