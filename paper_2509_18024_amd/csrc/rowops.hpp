@@ -52,10 +52,12 @@ struct alignas(16) WaveLds {
 // within each row of 16 lanes (xor 1, xor 2, half-row and row mirrors), then
 // the four row results through scalar registers.
 __device__ __forceinline__ int wave_max_key(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    // every lane has a source lane in these patterns; with bound_ctrl set the
+    // moves fold into the max instructions as DPP operands
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
     const int a = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
     const int b = max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
     return max(a, b);
@@ -343,8 +345,19 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     const float l = elim ? A[J] / piv : 0.f;
     if constexpr (KEEP) A[J] = elim ? l : A[J];
     if (lane == p) my_step = J;
+    // the pivot row in batches of 8: all readlanes of a batch first, into
+    // distinct scalars, then its updates, so that no update waits on the
+    // readlane just before it
 #pragma unroll
-    for (int c = J + 1; c < NF; ++c) A[c] = fmaf(-l, readlane_f(A[c], p), A[c]);
+    for (int c0 = J + 1; c0 < NF; c0 += 8) {
+        float pr[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (c0 + t < NF) pr[t] = readlane_f(A[c0 + t], p);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (c0 + t < NF) A[c0 + t] = fmaf(-l, pr[t], A[c0 + t]);
+    }
 #pragma unroll
     for (int q = 0; q < NR; ++q) rhs[q] = fmaf(-l, readlane_f(rhs[q], p), rhs[q]);
 }
@@ -482,7 +495,15 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
     const float l = elim ? G[J] / piv : 0.f;
     if (lane == p) my_step = J;
 #pragma unroll
-    for (int c = J + 1; c < WB_D; ++c) G[c] = fmaf(-l, readlane_f(G[c], p), G[c]);
+    for (int c0 = J + 1; c0 < WB_D; c0 += 8) {  // batched as in elim_step_u
+        float pr[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c0 + k < WB_D) pr[k] = readlane_f(G[c0 + k], p);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c0 + k < WB_D) G[c0 + k] = fmaf(-l, pr[k], G[c0 + k]);
+    }
     t = fmaf(-l, readlane_f(t, p), t);
 }
 
