@@ -342,7 +342,9 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     const float piv = readlane_f(A[J], p);
     ok = ok && (J >= nf || fabsf(piv) > tol);
     const bool elim = active && lane != p;
-    const float l = elim ? A[J] / piv : 0.f;
+    // multipliers by the hardware reciprocal (1 ulp) instead of an IEEE
+    // division sequence: one uniform reciprocal per step
+    const float l = elim ? A[J] * __builtin_amdgcn_rcpf(piv) : 0.f;
     if constexpr (KEEP) A[J] = elim ? l : A[J];
     if (lane == p) my_step = J;
     // the pivot row in batches of 8: all readlanes of a batch first, into
@@ -374,10 +376,10 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
     } else {
         p = J;
     }
-    const float d = readlane_f(A[J], p);
+    const float dinv = __builtin_amdgcn_rcpf(readlane_f(A[J], p));
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        const float x = readlane_f(rhs[q], p) / d;
+        const float x = readlane_f(rhs[q], p) * dinv;
         if (lane == p) xs[q * NF + J] = x;
         if (my_step < J) rhs[q] = fmaf(-A[J], x, rhs[q]);
     }
@@ -492,7 +494,7 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
     const float piv = readlane_f(G[J], p);
     ok = ok && fabsf(piv) > tol;
     const bool elim = active && lane != p;
-    const float l = elim ? G[J] / piv : 0.f;
+    const float l = elim ? G[J] * __builtin_amdgcn_rcpf(piv) : 0.f;
     if (lane == p) my_step = J;
 #pragma unroll
     for (int c0 = J + 1; c0 < WB_D; c0 += 8) {  // batched as in elim_step_u
@@ -515,7 +517,7 @@ __device__ __forceinline__ void wb_back_step(const float (&G)[WB_D], float &t, i
     const uint64_t bal = __ballot(my_step == J);
     int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
     p = __builtin_amdgcn_readfirstlane(p);
-    const float x = readlane_f(t, p) / readlane_f(G[J], p);
+    const float x = readlane_f(t, p) * __builtin_amdgcn_rcpf(readlane_f(G[J], p));
     if (lane == 0) zs[J] = x;
     if (my_step < J) t = fmaf(-G[J], x, t);
 }
