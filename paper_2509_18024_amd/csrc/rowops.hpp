@@ -305,11 +305,14 @@ __device__ __forceinline__ void gram(WaveLds &L, RowCtx &r, const Cut &c, int la
 
 // Diagonal penalty lambda n_i and identity padding for lanes >= nf.
 __device__ __forceinline__ void finish_system(float (&A)[NF], float &rhs, float lamn, int lane, int nf) {
-    const bool pad = lane >= nf;
+    // the lane through opaque_lane: else the 64 comparisons are hoisted out of
+    // the row loop and their results spilled
+    const int ol = opaque_lane(lane);
+    const bool pad = ol >= nf;
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
-        float v = A[b] + ((b == lane) ? lamn : 0.f);
-        A[b] = pad ? ((b == lane) ? 1.f : 0.f) : v;
+        float v = A[b] + ((b == ol) ? lamn : 0.f);
+        A[b] = pad ? ((b == ol) ? 1.f : 0.f) : v;
     }
     if (pad) rhs = 0.f;
 }
