@@ -30,7 +30,7 @@ CACHE = os.path.join(HERE, "tuning", "gfx950.json")
 
 DEFAULT = {"heavy_min_degree": 1024, "heavy_chunk": 1024, "light_blocks": 0}
 SPACE = {
-    "heavy_min_degree": [256, 512, 1024, 2048],
+    "heavy_min_degree": [128, 192, 256, 384, 512, 1024, 2048],
     "heavy_chunk": [512, 1024, 2048, 4096],
     "light_blocks": [0, 1024, 2048, 4096],
 }
@@ -106,7 +106,9 @@ def tune(torch, prob, gpu_csr, budget, precision, stream=None, log=None, path: O
     best_ms = time_config(torch, prob, gpu_csr, budget, precision, best, stream)
     trials = [(dict(best), best_ms)]
     t0 = time.time()
-    for knob in ("heavy_min_degree", "heavy_chunk", "light_blocks"):
+    # two rounds of coordinate descent: the best degree limit depends on the
+    # grid of the light-row kernels and the other way round
+    for knob in ("heavy_min_degree", "heavy_chunk", "light_blocks") * 2:
         for val in SPACE[knob]:
             if val == best[knob]:
                 continue
