@@ -146,6 +146,80 @@ __device__ __forceinline__ void tie_pass(WaveLds &L, RowCtx &r, int lane, bool t
     }
 }
 
+// Compare-exchange leaving the larger key in a.
+__device__ __forceinline__ void cex_desc(int &a, int &b) {
+    const int hi = max(a, b);
+    b = min(a, b);
+    a = hi;
+}
+
+// Bitonic sort of N keys (N a power of two) into descending order.
+template <int N>
+__device__ __forceinline__ void bitonic_sort_desc(int (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    if ((i & k) == 0) cex_desc(v[i], v[l]);
+                    else cex_desc(v[l], v[i]);
+                }
+            }
+}
+
+// Top-s of the lane's column for the larger classes, by blocks of SMAX keys:
+// each block is sorted, merged with the kept keys (both descending) by one
+// bitonic split, which leaves the SMAX largest of the two as a bitonic
+// sequence, and that is sorted again.  The same kept multiset, threshold and
+// largest dropped key as select_net, in about a third of the instructions.
+template <int SMAX>
+__device__ __forceinline__ Cut select_merge(WaveLds &L, RowCtx &r, int s, int lane) {
+    int kept_[SMAX];
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) kept_[j] = (j < SMAX - s) ? 0x7FFFFFFF : -1;
+    int D = -1;  // largest key that fell out
+    for (int k0 = 0; k0 < r.n; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int m = min(CK, r.n - k0);
+        for (int b0 = 0; b0 < m; b0 += SMAX) {
+            int blk[SMAX];
+#pragma unroll
+            for (int j = 0; j < SMAX; ++j) blk[j] = b0 + j < m ? key_of(L.X[b0 + j][lane]) : -1;
+            bitonic_sort_desc<SMAX>(blk);
+#pragma unroll
+            for (int j = 0; j < SMAX; ++j) {
+                const int a = kept_[j], b = blk[SMAX - 1 - j];
+                kept_[j] = max(a, b);
+                D = max(D, min(a, b));
+            }
+            // kept_ is bitonic: merge it into descending order
+#pragma unroll
+            for (int j = SMAX >> 1; j > 0; j >>= 1)
+#pragma unroll
+                for (int i = 0; i < SMAX; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) cex_desc(kept_[i], kept_[l]);
+                }
+        }
+    }
+    Cut c;
+    c.T = kept_[SMAX - 1];
+    c.none = false;
+    c.all = false;
+    int gt = 0;
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) gt += kept_[j] > c.T;
+    gt -= SMAX - s;
+    const int need = s - gt;
+    const bool tie = (D == c.T);
+    c.K = 0x7FFFFFFF;
+    tie_pass(L, r, lane, tie, c.T, need, c.K);
+    return c;
+}
+
 // Top-s by an insertion network of SMAX registers kept in descending order.
 // Unused slots (SMAX - s of them) hold INT_MAX and pass every key through.
 template <int SMAX>
