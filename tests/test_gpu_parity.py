@@ -125,6 +125,50 @@ def test_core_select_ties_and_item_side(ora):
     als.close()
 
 
+def merge_class_problem(grid: bool):
+    """Users with 90 to 499 ratings at r = 1/10: budgets 9 to 49, so the light
+    rows take the block-merge selection (s up to 16 and 32) over several
+    64-entry chunks with partial blocks, and the rest are heavy rows.  With
+    `grid`, item factors lie on a 1/16 grid in [-1, 1]: many exact ties."""
+    rng = np.random.default_rng(71 + int(grid))
+    n_u, n_m, nf = 48, 640, 64
+    deg = rng.integers(90, 500, size=n_u)
+    rp = np.zeros(n_u + 1, np.int64)
+    rp[1:] = np.cumsum(deg)
+    ci = np.concatenate([np.sort(rng.choice(n_m, size=d, replace=False)) for d in deg]).astype(np.int32)
+    val = rng.normal(3.0, 1.0, size=len(ci)).astype(np.float32)
+    if grid:
+        M0 = (rng.integers(-16, 17, size=(n_m, nf)) / 16.0).astype(np.float32)
+    else:
+        M0 = rng.normal(0.0, 0.5, size=(n_m, nf)).astype(np.float32)
+    return synth.Problem("merge" + ("_grid" if grid else ""), n_u, n_m, nf, rp, ci, val, 0.05, 1, 10, 1, 1, M0)
+
+
+@gpu
+@pytest.mark.parametrize("grid", [False, True])
+def test_block_merge_selection_and_sweep(ora, grid):
+    import torch
+    p = merge_class_problem(grid)
+    note(f"[block-merge select] grid={grid} n_u={p.n_u} degrees {int(np.diff(p.row_ptr).min())}.."
+         f"{int(np.diff(p.row_ptr).max())}")
+    als = make_als(p)
+    M = torch.from_numpy(p.M0).cuda()
+    sel_ptr, sel = als.core_select(0, M, 0, p.n_u)
+    torch.cuda.synchronize()
+    rp, rs = ora.core_select_rows(np.arange(p.n_u), p.row_ptr, p.col_idx, p.M0.astype(np.float64),
+                                  p.budget_num, p.budget_den, p.min_keep)
+    assert np.array_equal(sel_ptr.cpu().numpy(), rp)
+    assert np.array_equal(sel.cpu().numpy(), rs)
+    U = als.half_sweep_users(M)
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), p.lam,
+                           p.budget_num, p.budget_den, p.min_keep)
+    err = rel_fro(U.cpu().numpy(), Uo)
+    note(f"  users rel err {err:.3e}")
+    assert err <= 1e-4
+    als.close()
+
+
 @gpu
 @pytest.mark.parametrize("which", range(5))
 def test_half_sweeps_match_oracle(ora, which):
