@@ -31,7 +31,7 @@ __device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, in
     if constexpr (SEL == CLS_NET1) return select_net<1>(L, r, s, lane);
     else if constexpr (SEL == CLS_NET2) return select_net<2>(L, r, s, lane);
     else if constexpr (SEL == CLS_NET4) return select_net<4>(L, r, s, lane);
-    else if constexpr (SEL == CLS_NET8) return select_net<8>(L, r, s, lane);
+    else if constexpr (SEL == CLS_NET8) return select_merge<8>(L, r, s, lane);
     else if constexpr (SEL == CLS_NET16) return select_merge<16>(L, r, s, lane);
     else return select_merge<32>(L, r, s, lane);
 }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(WPB * 64) void k_select(SelectArgs a) {
                 case CLS_NET1: c = select_net<1>(L, r, s, lane); break;
                 case CLS_NET2: c = select_net<2>(L, r, s, lane); break;
                 case CLS_NET4: c = select_net<4>(L, r, s, lane); break;
-                case CLS_NET8: c = select_net<8>(L, r, s, lane); break;
+                case CLS_NET8: c = select_merge<8>(L, r, s, lane); break;
                 case CLS_NET16: c = select_merge<16>(L, r, s, lane); break;
                 case CLS_NET32: c = select_merge<32>(L, r, s, lane); break;
                 default: c = Cut{a.cutT[t * 64 + lane], a.cutK[t * 64 + lane], false, false}; break;
