@@ -85,7 +85,7 @@ typedef struct {
                                     are split across workgroups; 0 = default 1024 */
     int32_t heavy_chunk;         /* entries per partial Gram of such rows; 0 = 1024 */
     int32_t heavy_pair_cap;      /* partial systems kept in scratch at once (sizes the
-                                    workspace); 0 = 32768 */
+                                    workspace); 0 = 65536 */
     int32_t light_blocks;        /* grid of the persistent light-row kernels, whose
                                     wavefronts take rows from an atomic counter;
                                     0 = one row per wavefront */

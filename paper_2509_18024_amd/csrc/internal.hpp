@@ -26,7 +26,7 @@ constexpr int HEAVY_CAP = 62;
 // Defaults of the schedule (als_problem fields set to 0 select them).
 constexpr int DEFAULT_HEAVY_N = 1024;    // light rows have degree <= this
 constexpr int DEFAULT_CHUNK = 1024;      // entries per partial Gram of a heavy row
-constexpr int64_t PAIR_CAP = 32768;      // partial systems held in scratch at once
+constexpr int64_t PAIR_CAP = 65536;      // partial systems held in scratch at once
 
 // Degree classes that schedule a half-sweep.  Light rows (degree <= heavy_n
 // and budget s <= 32) are solved by one wavefront each: FULL when s == n
