@@ -41,12 +41,18 @@ __device__ __forceinline__ int opaque_lane(int lane) {
     return lane;
 }
 
-struct alignas(16) WaveLds {
-    float X[CK][NF + 4];      // staged design rows (select, Gram)
-    float y[CK];
+// One wavefront's LDS: ROWS staged design rows (a chunk), their ratings and
+// the solve's scratch.  The classes of short rows stage 32-row chunks, which
+// halves the LDS per wavefront.
+template <int ROWS>
+struct alignas(16) WaveLdsT {
+    static constexpr int rows = ROWS;
+    float X[ROWS][NF + 4];    // staged design rows (select, Gram)
+    float y[ROWS];
     float urhs[2 * NF];       // solve: solution components parked by the back substitution
-    double rres[CK];          // refinement: residuals y_k - x_k . u of the staged rows
+    double rres[ROWS];        // refinement: residuals y_k - x_k . u of the staged rows
 };
+using WaveLds = WaveLdsT<CK>;
 
 // Largest value over the wave of a non-negative-or-(-1) integer key: DPP
 // within each row of 16 lanes (xor 1, xor 2, half-row and row mirrors), then
@@ -76,37 +82,38 @@ struct RowCtx {
 };
 
 // Gather chunk [k0, k0 + min(CK, n - k0)) of the design matrix into LDS.
-__device__ __forceinline__ void stage(WaveLds &L, RowCtx &r, int k0, int lane) {
+template <class LDS>
+__device__ __forceinline__ void stage(LDS &L, RowCtx &r, int k0, int lane) {
     if (r.staged == k0) return;
     wave_sync();
-    const int cnt = min(CK, r.n - k0);
+    const int cnt = min(LDS::rows, r.n - k0);
     int col = 0;
     float yv = 0.f;
     if (lane < cnt) {
         col = r.idx[r.beg + k0 + lane];
         if (r.val) yv = r.val[r.beg + k0 + lane];
     }
-    if (lane < CK) L.y[lane] = yv;
+    if (lane < LDS::rows) L.y[lane] = yv;
     // Gathers are unconditional (positions past cnt read factor row 0, which
     // exists) so the whole chunk's loads are in flight together; the padding
     // is zeroed afterwards.
     if (r.vec4) {
-        float4 v[CK / 4];
+        float4 v[LDS::rows / 4];
 #pragma unroll
-        for (int t = 0; t < CK / 4; ++t) {
+        for (int t = 0; t < LDS::rows / 4; ++t) {
             const int kk = t * 4 + (lane >> 4);
             const int c = __shfl(col, kk);
             v[t] = *reinterpret_cast<const float4 *>(r.other + (size_t)c * NF + (lane & 15) * 4);
         }
 #pragma unroll
-        for (int t = 0; t < CK / 4; ++t) {
+        for (int t = 0; t < LDS::rows / 4; ++t) {
             const int kk = t * 4 + (lane >> 4);
             if (kk >= cnt) v[t] = make_float4(0.f, 0.f, 0.f, 0.f);
             *reinterpret_cast<float4 *>(&L.X[kk][(lane & 15) * 4]) = v[t];
         }
     } else {
         const int lc = min(lane, r.nf - 1);
-        for (int kk = 0; kk < CK; ++kk) {
+        for (int kk = 0; kk < LDS::rows; ++kk) {
             const int c = __shfl(col, kk);
             const float v = r.other[(size_t)c * r.nf + lc];
             L.X[kk][lane] = (kk < cnt && lane < r.nf) ? v : 0.f;
@@ -130,12 +137,13 @@ __device__ __forceinline__ bool kept(const Cut &c, int key, int pos) {
 }
 
 // Position of the need-th key equal to T in ascending order (lanes with tie).
-__device__ __forceinline__ void tie_pass(WaveLds &L, RowCtx &r, int lane, bool tie, int T, int need, int &K) {
+template <class LDS>
+__device__ __forceinline__ void tie_pass(LDS &L, RowCtx &r, int lane, bool tie, int T, int need, int &K) {
     if (__ballot(tie) == 0ull) return;
     int cnt = 0;
-    for (int k0 = 0; k0 < r.n; k0 += CK) {
+    for (int k0 = 0; k0 < r.n; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, r.n - k0);
+        const int m = min(LDS::rows, r.n - k0);
         for (int k = 0; k < m; ++k) {
             const int key = key_of(L.X[k][lane]);
             if (tie && key == T) {
@@ -175,15 +183,15 @@ __device__ __forceinline__ void bitonic_sort_desc(int (&v)[N]) {
 // bitonic split, which leaves the SMAX largest of the two as a bitonic
 // sequence, and that is sorted again.  The same kept multiset, threshold and
 // largest dropped key as select_net, in about a third of the instructions.
-template <int SMAX>
-__device__ __forceinline__ Cut select_merge(WaveLds &L, RowCtx &r, int s, int lane) {
+template <int SMAX, class LDS>
+__device__ __forceinline__ Cut select_merge(LDS &L, RowCtx &r, int s, int lane) {
     int kept_[SMAX];
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) kept_[j] = (j < SMAX - s) ? 0x7FFFFFFF : -1;
     int D = -1;  // largest key that fell out
-    for (int k0 = 0; k0 < r.n; k0 += CK) {
+    for (int k0 = 0; k0 < r.n; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, r.n - k0);
+        const int m = min(LDS::rows, r.n - k0);
         for (int b0 = 0; b0 < m; b0 += SMAX) {
             int blk[SMAX];
 #pragma unroll
@@ -222,15 +230,15 @@ __device__ __forceinline__ Cut select_merge(WaveLds &L, RowCtx &r, int s, int la
 
 // Top-s by an insertion network of SMAX registers kept in descending order.
 // Unused slots (SMAX - s of them) hold INT_MAX and pass every key through.
-template <int SMAX>
-__device__ __forceinline__ Cut select_net(WaveLds &L, RowCtx &r, int s, int lane) {
+template <int SMAX, class LDS>
+__device__ __forceinline__ Cut select_net(LDS &L, RowCtx &r, int s, int lane) {
     int kept_[SMAX];
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) kept_[j] = (j < SMAX - s) ? 0x7FFFFFFF : -1;
     int D = -1;  // largest key that fell out of the network
-    for (int k0 = 0; k0 < r.n; k0 += CK) {
+    for (int k0 = 0; k0 < r.n; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, r.n - k0);
+        const int m = min(LDS::rows, r.n - k0);
         for (int k = 0; k < m; ++k) {
             int v = key_of(L.X[k][lane]);
 #pragma unroll
@@ -259,15 +267,16 @@ __device__ __forceinline__ Cut select_net(WaveLds &L, RowCtx &r, int s, int lane
 
 // Row a of X*^T X and entry a of X*^T y for the lane's column, summed over
 // positions [kb, ke) of the row (chunks of CK staged in LDS; ascending k).
-__device__ __forceinline__ void gram_range(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+template <class LDS>
+__device__ __forceinline__ void gram_range(LDS &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
                                            float (&A)[NF], float &rhs) {
 #pragma unroll
     for (int b = 0; b < NF; ++b) A[b] = 0.f;
     rhs = 0.f;
     if (c.none) return;
-    for (int k0 = kb; k0 < ke; k0 += CK) {
+    for (int k0 = kb; k0 < ke; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, ke - k0);
+        const int m = min(LDS::rows, ke - k0);
         for (int k = 0; k < m; ++k) {
             const float xa = L.X[k][lane];
             const float w = kept(c, key_of(xa), k0 + k) ? xa : 0.f;
@@ -289,15 +298,16 @@ __device__ __forceinline__ void gram_range(WaveLds &L, RowCtx &r, const Cut &c, 
 // mask, then walks them in ascending order (the wave iterates as often as its
 // busiest lane).  Only the zero products of the unkept positions are skipped,
 // so the sums equal gram_range's.
-__device__ __forceinline__ void gram_range_sparse(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+template <class LDS>
+__device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
                                                   float (&A)[NF], float &rhs) {
 #pragma unroll
     for (int b = 0; b < NF; ++b) A[b] = 0.f;
     rhs = 0.f;
     if (c.none) return;
-    for (int k0 = kb; k0 < ke; k0 += CK) {
+    for (int k0 = kb; k0 < ke; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, ke - k0);
+        const int m = min(LDS::rows, ke - k0);
         uint64_t bits = 0;
         for (int k = 0; k < m; ++k)
             if (kept(c, key_of(L.X[k][lane]), k0 + k)) bits |= 1ull << k;
@@ -324,14 +334,15 @@ __device__ __forceinline__ void gram_range_sparse(WaveLds &L, RowCtx &r, const C
 // g_a parked in L.urhs[a]: over positions [kb, ke), lane a accumulates
 // rho_a = sum over kept k of x_ka (y_k - x_k . g) and b_a = sum over kept k of
 // x_ka y_k (the right-hand side of eq. core_ui).  Products in FP32, sums in FP64.
-__device__ __forceinline__ void resid_range(WaveLds &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
+template <class LDS>
+__device__ __forceinline__ void resid_range(LDS &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
                                             double &rho, double &bsum) {
     rho = 0.0;
     bsum = 0.0;
     if (c.none) return;
-    for (int k0 = kb; k0 < ke; k0 += CK) {
+    for (int k0 = kb; k0 < ke; k0 += LDS::rows) {
         stage(L, r, k0, lane);
-        const int m = min(CK, ke - k0);
+        const int m = min(LDS::rows, ke - k0);
         float rk = 0.f;
         if (lane < m) {
             float dot = 0.f;
@@ -345,7 +356,7 @@ __device__ __forceinline__ void resid_range(WaveLds &L, RowCtx &r, const Cut &c,
             }
             rk = L.y[lane] - dot;
         }
-        L.rres[lane] = (double)rk;
+        if (lane < LDS::rows) L.rres[lane] = (double)rk;
         wave_sync();
         for (int k = 0; k < m; ++k) {
             const float x = L.X[k][lane];
@@ -373,7 +384,8 @@ __device__ __forceinline__ double rel_residual(double rho, double bsum, int lane
     return bb > 0.0 ? sqrt(rr / bb) : __builtin_inf();
 }
 
-__device__ __forceinline__ void gram(WaveLds &L, RowCtx &r, const Cut &c, int lane, float (&A)[NF], float &rhs) {
+template <class LDS>
+__device__ __forceinline__ void gram(LDS &L, RowCtx &r, const Cut &c, int lane, float (&A)[NF], float &rhs) {
     gram_range(L, r, c, 0, r.n, lane, A, rhs);
 }
 
@@ -501,9 +513,9 @@ __device__ __forceinline__ void back_all_u(std::integer_sequence<int, J...>, con
 // Solve the register-resident system for NR right-hand sides at once; returns
 // false when a pivot of the first nf steps is <= tol.  On success x[q] holds
 // component `lane` of the solution for right-hand side q.
-template <bool PIVOT, int NR>
+template <bool PIVOT, int NR, class LDS>
 __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
-                                        float (&x)[NR], WaveLds &L) {
+                                        float (&x)[NR], LDS &L) {
     int my_step = NF;  // elimination step at which this lane's row was the pivot
     bool ok = true;
     elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
@@ -518,9 +530,9 @@ __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int la
     return true;
 }
 
-template <bool PIVOT>
+template <bool PIVOT, class LDS>
 __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
-                                      WaveLds &L) {
+                                      LDS &L) {
     float r[1] = {rhs};
     float x[1];
     const bool ok = solve_n<PIVOT, 1>(A, r, lane, nf, tol, x, L);
@@ -539,7 +551,8 @@ __device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lan
 }
 
 // Back substitution of an eliminated right-hand side; x = component `lane`.
-__device__ __forceinline__ float lu_back(const float (&A)[NF], float (&rhs)[1], int lane, int my_step, WaveLds &L) {
+template <class LDS>
+__device__ __forceinline__ float lu_back(const float (&A)[NF], float (&rhs)[1], int lane, int my_step, LDS &L) {
     wave_sync();
     back_all_u<true, 1>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, my_step, L.urhs);
     wave_sync();
@@ -614,15 +627,24 @@ __device__ __forceinline__ bool wb_lu(std::integer_sequence<int, J...>, float (&
 // the lane's column).  Returns false, leaving L.X untouched, when the guard
 // fails; returns false after masking L.X in place when G is singular (the
 // caller re-stages).  On success u is component `lane` of the solution.
-__device__ __forceinline__ bool woodbury_solve(WaveLds &L, const Cut &c, int lane, int n, int nf, float lam,
+template <class LDS>
+__device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, int n, int nf, float lam,
                                                float lamn, bool &masked, float &u) {
     masked = false;
-    // lane k holds design row k (rows n.. are the staged zero padding)
+    static_assert(LDS::rows >= WB_D, "the Woodbury form stages the whole row");
+    // lane k holds design row k (rows n.. are the staged zero padding; lanes
+    // past the staged rows hold zeros)
     float xk[NF];
     float nrm = 0.f;
+    const int kr = min(lane, LDS::rows - 1);
+    const float lv = lane < LDS::rows ? 1.f : 0.f;
 #pragma unroll
     for (int b4 = 0; b4 < NF / 4; ++b4) {
-        const float4 v = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
+        float4 v = *reinterpret_cast<const float4 *>(&L.X[kr][4 * b4]);
+        v.x *= lv;
+        v.y *= lv;
+        v.z *= lv;
+        v.w *= lv;
         xk[4 * b4 + 0] = v.x;
         xk[4 * b4 + 1] = v.y;
         xk[4 * b4 + 2] = v.z;

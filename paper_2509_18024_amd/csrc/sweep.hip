@@ -26,8 +26,10 @@ namespace coreals {
 
 namespace {
 
-template <int SEL>
-__device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, int lane) {
+constexpr int WB_WAVES = 3;  // waves per SIMD of the Woodbury-class kernels
+
+template <int SEL, class LDS>
+__device__ __forceinline__ Cut select_for_class(LDS &L, RowCtx &r, int s, int lane) {
     if constexpr (SEL == CLS_NET1) return select_net<1>(L, r, s, lane);
     else if constexpr (SEL == CLS_NET2) return select_net<2>(L, r, s, lane);
     else if constexpr (SEL == CLS_NET4) return select_net<4>(L, r, s, lane);
@@ -41,10 +43,13 @@ __device__ __forceinline__ Cut select_for_class(WaveLds &L, RowCtx &r, int s, in
 // is at most a.tol; otherwise the row is solved exactly as in the sweep.
 template <int CLS, bool CHECK>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
-    __shared__ WaveLds lds[WPB];
+    // the two smallest classes solve in Woodbury form from one chunk of at
+    // most WB_D rows: 32-row chunks, half the LDS per wavefront
+    using LDS = WaveLdsT<(!CHECK && (CLS == CLS_NET1 || CLS == CLS_NET2)) ? WB_D : CK>;
+    __shared__ LDS lds[WPB];
     const int w = wave_index();
     const int lane0 = threadIdx.x & 63;
-    WaveLds &L = lds[w];
+    LDS &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
 
     // persistent launch: each wavefront takes the next row of the class from
@@ -139,9 +144,18 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
 __global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL, false>(a); }
 
 // Core light rows: the pivot search raises register demand; capping the
-// kernel at two waves per SIMD (a few spills) beats one wave per SIMD.
+// kernel at two waves per SIMD beats one wave per SIMD.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
+    sweep_rows<CLS, false>(a);
+}
+
+// The two smallest classes (Woodbury form, 32-row LDS chunks): latency bound,
+// so more waves per SIMD; the registers of the rarely taken 64 x 64 fallback
+// spill instead.
+template <int CLS>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAVES, WB_WAVES))) void k_sweep_wb(
+    SweepArgs a) {
     sweep_rows<CLS, false>(a);
 }
 
@@ -213,6 +227,8 @@ hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
     } else {
         if constexpr (CLS == CLS_FULL)
             hipLaunchKernelGGL(k_sweep_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+        else if constexpr (CLS == CLS_NET1 || CLS == CLS_NET2)
+            hipLaunchKernelGGL(k_sweep_wb<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
         else
             hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
     }
