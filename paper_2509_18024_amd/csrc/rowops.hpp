@@ -64,9 +64,11 @@ __device__ __forceinline__ int wave_max_key(int v) {
     v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm [2,3,0,1]
     v = max(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
     v = max(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
-    const int a = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
-    const int b = max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
-    return max(a, b);
+    // across rows: lane 15 into row 1 and lane 47 into row 3, then lane 31
+    // into rows 2 and 3; lane 63 ends with the wave's maximum
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Per-row view used by the device helpers.
@@ -418,12 +420,12 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     int p;
     bool active;
     if constexpr (PIVOT) {
+        // the candidate's magnitude with its low 6 bits replaced by 63 - lane:
+        // one maximum gives the pivot lane (the first of equal candidates;
+        // magnitudes within 2^-17 of each other count as equal)
         active = my_step == NF;
-        const int cand = active ? __float_as_int(fabsf(A[J])) : -1;
-        const int mx = wave_max_key(cand);
-        const uint64_t bal = __ballot(active && cand == mx);
-        p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
-        p = __builtin_amdgcn_readfirstlane(p);
+        const int cand = active ? ((__float_as_int(fabsf(A[J])) & ~63) | (63 - lane)) : -1;
+        p = 63 - (wave_max_key(cand) & 63);
     } else {
         active = lane >= J;
         p = J;
@@ -576,11 +578,8 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
                                              bool &ok) {
     if (J >= n) return;  // uniform: the system has n rows
     const bool active = my_step == WB_D + 1;
-    const int cand = active ? __float_as_int(fabsf(G[J])) : -1;
-    const int mx = wave_max_key(cand);
-    const uint64_t bal = __ballot(active && cand == mx);
-    int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
-    p = __builtin_amdgcn_readfirstlane(p);
+    const int cand = active ? ((__float_as_int(fabsf(G[J])) & ~63) | (63 - lane)) : -1;  // as in elim_step_u
+    const int p = 63 - (wave_max_key(cand) & 63);
     const float piv = readlane_f(G[J], p);
     ok = ok && fabsf(piv) > tol;
     const bool elim = active && lane != p;
