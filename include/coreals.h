@@ -61,6 +61,10 @@ typedef enum {
 } als_precision;
 
 #define ALS_VALIDATE 1u   /* check ratings for NaN/Inf in als_init */
+#define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
+                                 even where 32-bit buffer offsets would do (the
+                                 path taken for factor matrices of 2^24 rows or
+                                 2^31 bytes and more; slower, for tests) */
 #define ALS_USERS_ONLY 2u /* users side only: no column view is built, and
                              half_sweep_items, core_select(side 1) and objective
                              return ALS_E_STATE (contexts of new users to fold
@@ -77,7 +81,7 @@ typedef struct {
     uint32_t budget_den;         /* 0 < r <= 1; r = 1 is full-data ALS              */
     int32_t min_keep;            /* s_i = min(n_i, max(min_keep, floor(n_i r)))     */
     int32_t precision;           /* als_precision                                   */
-    uint32_t flags;              /* ALS_VALIDATE | ALS_USERS_ONLY                   */
+    uint32_t flags;              /* ALS_VALIDATE | ALS_USERS_ONLY | ALS_GENERIC_GATHERS */
     void *stream;                /* hipStream_t                                     */
     void *workspace;             /* device buffer, at least als_workspace_size bytes */
     size_t workspace_bytes;

@@ -35,7 +35,8 @@ class CoreALS:
                  val: torch.Tensor, lam: float, budget: Tuple[int, int] = (1, 1), min_keep: int = 1,
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
-                 light_blocks: int = 0, graphs: bool = False, users_only: bool = False):
+                 light_blocks: int = 0, graphs: bool = False, users_only: bool = False,
+                 generic_gathers: bool = False):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -52,7 +53,8 @@ class CoreALS:
         p.budget_num, p.budget_den = int(budget[0]), int(budget[1])
         p.min_keep = int(min_keep)
         p.precision = int(precision)
-        p.flags = (capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
+        p.flags = ((capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
+                   | (capi.ALS_GENERIC_GATHERS if generic_gathers else 0))
         p.stream = self.stream.cuda_stream
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)

@@ -17,6 +17,7 @@ ALS_OK, ALS_E_ARG, ALS_E_INDEX, ALS_E_VALUE, ALS_E_NOMEM, ALS_E_DEVICE, ALS_E_ST
 ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES, ALS_PREC_AUTO = 0, 1, 2, 3
 ALS_VALIDATE = 1
 ALS_USERS_ONLY = 2
+ALS_GENERIC_GATHERS = 4
 FOLDIN_BF16, FOLDIN_FP32 = 0, 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",

@@ -200,7 +200,8 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.idx = S.idx;
         h.val = S.val;
         h.other = other;
-        h.other_rows = side == 0 ? c->p.n_m : c->p.n_u;
+        // 0: unknown size, which makes the heavy-row kernels use 64-bit gathers
+        h.other_rows = (c->p.flags & ALS_GENERIC_GATHERS) ? 0 : (side == 0 ? c->p.n_m : c->p.n_u);
         h.out = out;
         h.rows = S.perm + S.class_off[CLS_HEAVY];
         h.count = H.n_heavy;
@@ -228,7 +229,8 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.path = nullptr;
         h.rho = nullptr;
         if (c->p.budget_num < c->p.budget_den) {
-            if (c->key16) {
+            if (c->key16 && h.other_rows > 0 && h.other_rows * h.nf * 4 <= (int64_t)0x7FFFFFFF) {
+                // (the selection reads the copy only where it gathers by buffer loads)
                 HIP_CHECK(c, launch_key16(other, h.other_rows * h.nf, c->key16, c->stream));
                 h.key16 = c->key16;
             }
@@ -553,7 +555,7 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
         h.ptr = S.ptr;
         h.idx = S.idx;
         h.other = other;
-        h.other_rows = side == 0 ? c->p.n_m : c->p.n_u;
+        h.other_rows = (c->p.flags & ALS_GENERIC_GATHERS) ? 0 : (side == 0 ? c->p.n_m : c->p.n_u);
         h.rows = nullptr;
         h.count = r1 - r0;
         h.nf = c->p.n_f;

@@ -663,6 +663,10 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
 constexpr int GF_PAIRS = 16;               // entry pairs gathered per batch
 constexpr uint32_t GF_NONE = 0x80000000u;  // an offset past any factor matrix
 
+// BUF: buffer loads with 32-bit offsets and the zero padding of out-of-range
+// offsets (factor matrices below 2^24 rows and 2^31 bytes); else 64-bit
+// addresses, clamped rows and explicit zeros.
+template <bool BUF>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_heavy_gram_f32(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
@@ -673,9 +677,12 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int nf = a.nf;
     const uint32_t off0 = m < nf ? 4 * m : GF_NONE, off1 = 32 + m < nf ? 4 * (32 + m) : GF_NONE;
     const int stride = 4 * nf;
-    const int rows = (int)a.other_rows;  // column `rows`: past the matrix
+    // padding column: past the matrix (BUF) or -1
+    const int rows = BUF ? (int)a.other_rows : -1;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(a.other), (short)0, (int)(a.other_rows * nf * 4), 0x00020000);
+        const_cast<float *>(a.other), (short)0, BUF ? (int)(a.other_rows * nf * 4) : 0, 0x00020000);
+    const float *col0p = a.other + min(m, nf - 1), *col1p = a.other + min(32 + m, nf - 1);
+    const bool live0 = m < nf, live1 = 32 + m < nf;
     for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
         const int64_t slot = a.pair_slot[p];
         const int chunk = a.pair_chunk[p];
@@ -728,9 +735,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
                 for (int q = 0; q < GF_PAIRS; ++q) {
                     const int col = s_col[w][j0 + 2 * q + h];
-                    const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
-                    x0[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
-                    x1[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
+                    if constexpr (BUF) {
+                        const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
+                        x0[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
+                        x1[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
+                    } else {
+                        const size_t ro = (size_t)max(col, 0) * nf;
+                        const float u0 = col0p[ro], u1 = col1p[ro];
+                        x0[q] = (col >= 0 && live0) ? u0 : 0.f;
+                        x1[q] = (col >= 0 && live1) ? u1 : 0.f;
+                    }
                 }
                 // every gather of the batch is issued before the first use
                 __builtin_amdgcn_sched_barrier(0);
@@ -987,10 +1001,11 @@ hipError_t launch_heavy_select(const HeavyArgs &a, int64_t row_begin, hipStream_
 hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
     if (pair_end <= pair_begin) return hipSuccess;
     // buffer offsets are 24-bit products row * 4 n_f plus 32-bit sums
-    if (a.other_rows <= 0 || a.other_rows >= (1 << 24) || a.other_rows * (int64_t)a.nf * 4 > (int64_t)0x7FFFFFFF)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_heavy_gram_f32, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
-                       a, pair_begin, pair_end);
+    const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
+                     a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
+    const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
+    if (buf) hipLaunchKernelGGL(k_heavy_gram_f32<true>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else hipLaunchKernelGGL(k_heavy_gram_f32<false>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
     return hipGetLastError();
 }
 

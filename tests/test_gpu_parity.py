@@ -368,12 +368,16 @@ HEAVY_KW = dict(heavy_min_degree=64, heavy_chunk=32, heavy_pair_cap=64)
 
 
 @gpu
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("which", range(3))
-def test_heavy_rows_match_oracle(ora, which):
+def test_heavy_rows_match_oracle(ora, which, generic):
+    """generic: the heavy-row selection and Gram gather with 64-bit addresses,
+    the path of factor matrices too large for 32-bit buffer offsets."""
     import torch
     name, p = heavy_cases()[which]
-    note(f"[heavy] {name} n_u={p.n_u} n_m={p.n_m} n_f={p.n_f} r={p.budget_num}/{p.budget_den}")
-    als = make_als(p, **HEAVY_KW)
+    note(f"[heavy] {name} n_u={p.n_u} n_m={p.n_m} n_f={p.n_f} r={p.budget_num}/{p.budget_den} "
+         f"generic={generic}")
+    als = make_als(p, generic_gathers=generic, **HEAVY_KW)
     from paper_2509_18024_amd import capi
     counts = capi.als_class_counts(als.ctx)
     note(f"  classes users {counts[0]} items {counts[1]}")
@@ -464,7 +468,8 @@ def test_small_rows_woodbury_form(ora, budget, scale):
 
 
 @gpu
-def test_heavy_selection_full_radix_with_ties(ora):
+@pytest.mark.parametrize("generic", [False, True])
+def test_heavy_selection_full_radix_with_ties(ora, generic):
     """Factor magnitudes uniform in [1, 2) on a 2^-11 grid: in a row of 60000
     ratings about 230 keys share the threshold's 16-bit prefix, more than the
     candidate lists hold (all four radix passes run), and about 30 keys equal
@@ -480,8 +485,8 @@ def test_heavy_selection_full_radix_with_ties(ora):
     M0 = ((1.0 + np.floor(rng.random((n_m, nf)) * 2048.0) / 2048.0)
           * rng.choice([-1.0, 1.0], size=(n_m, nf))).astype(np.float32)
     p = synth.Problem("grid", n_u, n_m, nf, rp, ci, val, 0.05, 1, 10, 1, 1, M0)
-    note("[full radix + ties] n=60000, magnitudes in [1, 2) on a 2^-11 grid")
-    als = make_als(p, heavy_min_degree=64)
+    note(f"[full radix + ties] n=60000, magnitudes in [1, 2) on a 2^-11 grid, generic={generic}")
+    als = make_als(p, heavy_min_degree=64, generic_gathers=generic)
     sel_ptr, sel = als.core_select(0, torch.from_numpy(M0).cuda(), 0, n_u)
     torch.cuda.synchronize()
     rpo, rso = ora.core_select_rows(np.arange(n_u), rp, ci, M0.astype(np.float64), 1, 10, 1)
