@@ -83,18 +83,13 @@ struct RowCtx {
     int staged;  // chunk start currently in LDS, -1 if none
 };
 
-// Gather chunk [k0, k0 + min(CK, n - k0)) of the design matrix into LDS.
+// Gather chunk [k0, k0 + cnt) of the design matrix into LDS, cnt = min(rows,
+// n - k0), from its column indices and ratings already loaded: lane j < cnt
+// holds those of position k0 + j (col = 0 and yv = 0 elsewhere).
 template <class LDS>
-__device__ __forceinline__ void stage(LDS &L, RowCtx &r, int k0, int lane) {
-    if (r.staged == k0) return;
+__device__ __forceinline__ void stage_loaded(LDS &L, RowCtx &r, int k0, int col, float yv, int lane) {
     wave_sync();
     const int cnt = min(LDS::rows, r.n - k0);
-    int col = 0;
-    float yv = 0.f;
-    if (lane < cnt) {
-        col = r.idx[r.beg + k0 + lane];
-        if (r.val) yv = r.val[r.beg + k0 + lane];
-    }
     if (lane < LDS::rows) L.y[lane] = yv;
     // Gathers are unconditional (positions past cnt read factor row 0, which
     // exists) so the whole chunk's loads are in flight together; the padding
@@ -123,6 +118,20 @@ __device__ __forceinline__ void stage(LDS &L, RowCtx &r, int k0, int lane) {
     }
     r.staged = k0;
     wave_sync();
+}
+
+// Gather chunk [k0, k0 + min(rows, n - k0)) of the design matrix into LDS.
+template <class LDS>
+__device__ __forceinline__ void stage(LDS &L, RowCtx &r, int k0, int lane) {
+    if (r.staged == k0) return;
+    const int cnt = min(LDS::rows, r.n - k0);
+    int col = 0;
+    float yv = 0.f;
+    if (lane < cnt) {
+        col = r.idx[r.beg + k0 + lane];
+        if (r.val) yv = r.val[r.beg + k0 + lane];
+    }
+    stage_loaded(L, r, k0, col, yv, lane);
 }
 
 // Selection result for the lane's column: k is kept iff
@@ -585,8 +594,10 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
     const bool elim = active && lane != p;
     const float l = elim ? G[J] * __builtin_amdgcn_rcpf(piv) : 0.f;
     if (lane == p) my_step = J;
+    // columns n.. of every row stay as they are: the pivot row is zero there
 #pragma unroll
     for (int c0 = J + 1; c0 < WB_D; c0 += 8) {  // batched as in elim_step_u
+        if (c0 >= n) break;
         float pr[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k)

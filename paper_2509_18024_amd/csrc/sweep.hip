@@ -41,7 +41,9 @@ __device__ __forceinline__ Cut select_for_class(LDS &L, RowCtx &r, int s, int la
 // CHECK (fold-in answers): the row's candidate solution a.guess[i] is kept when
 // the relative residual of the row's system (the one the sweep would solve)
 // is at most a.tol; otherwise the row is solved exactly as in the sweep.
-template <int CLS, bool CHECK>
+// STRIDED: rows dealt out by wave index with the next rows' indices
+// prefetched (the grid must be resident at once); else an atomic row queue.
+template <int CLS, bool CHECK, bool STRIDED>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     // the two smallest classes solve in Woodbury form from one chunk of at
     // most WB_D rows: 32-row chunks, half the LDS per wavefront
@@ -52,18 +54,13 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     LDS &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
 
-    // persistent launch: each wavefront takes the next row of the class from
-    // an atomic counter (rows are ordered by decreasing degree)
-    for (;;) {
-        unsigned int got = 0;
-        if (lane0 == 0) got = atomicAdd(a.queue, 1u);
-        const int64_t slot = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)got);
-        if (slot >= a.count) break;
-        const int lane = opaque_lane(lane0);
-        const int64_t i = a.perm[slot];
-        const int64_t beg = a.ptr[i];
-        const int n = (int)(a.ptr[i + 1] - beg);
+    // One row: i its index, [beg, beg + n) its entries; if STRIDED, col0 / y0
+    // hold the column indices and ratings of its first LDS chunk (lane j:
+    // entry j).
+    auto row = [&](int64_t i, int64_t beg, int n, int lane, int col0, float y0) {
         RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
+        if constexpr (STRIDED)
+            if (n > 0) stage_loaded(L, r, 0, col0, y0, lane);  // indices prefetched
         if (n == 0) {
             if (lane < a.nf) a.out[i * a.nf + lane] = 0.f;
             if (lane == 0) {
@@ -73,7 +70,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                     a.rho[i] = __builtin_inff();
                 }
             }
-            continue;
+            return;
         }
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
         const float lamn = (float)((double)a.lam * (double)n);
@@ -103,18 +100,18 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
             }
             if (accept) {
                 if (lane < a.nf) a.out[i * a.nf + lane] = g;
-                continue;
+                return;
             }
         }
         if constexpr (!CHECK && (CLS == CLS_NET1 || CLS == CLS_NET2)) {
             // few entries: the n x n Woodbury form of the same system
             if (n <= WB_D && s > 0 && a.lam > 0.f) {
-                stage(L, r, 0, lane);  // the whole row is chunk 0
+                stage(L, r, 0, lane);  // the whole row is chunk 0 (staged above)
                 bool masked;
                 float uw;
                 if (woodbury_solve(L, c, lane, n, a.nf, a.lam, lamn, masked, uw)) {
                     if (lane < a.nf) a.out[i * a.nf + lane] = uw;
-                    continue;
+                    return;
                 }
                 if (masked) r.staged = -1;  // L.X holds the masked rows: re-stage
             }
@@ -137,34 +134,107 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
             c = Cut{0, 0, false, true};
         }
         if (lane < a.nf) a.out[i * a.nf + lane] = u;
+    };
+
+    if constexpr (STRIDED) {
+        // Wave g takes rows g, g + G, g + 2G, ... of the class (G waves in the
+        // grid, all resident; rows of similar degree, so the shares balance),
+        // which lets the row bounds and indices of the next rows load while
+        // this one is solved: with two waves per SIMD the fetch latency of a
+        // row is otherwise exposed.  Pipeline: indices of row t + 1, bounds of
+        // row t + 2 and the row number of row t + 3 are fetched during row t.
+        const int64_t G = (int64_t)gridDim.x * WPB;
+        const int64_t cnt = a.count;
+        const int lane = opaque_lane(lane0);
+        // z = 0, opaque to the compiler: the prefetched values stay in vector
+        // registers (per-lane loads) and become scalars only when their row
+        // starts, so no wait for them is placed right after their loads
+        const int z = lane >> 6;
+        auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+        auto uni64 = [](int64_t v) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+            return (int64_t)(((uint64_t)hi << 32) | lo);
+        };
+        // row number of slot t (row 0, which exists, past the class: never solved)
+        auto row_of = [&](int64_t t) -> int { return t < cnt ? a.perm[t + z] : 0; };
+        int64_t slot = (int64_t)blockIdx.x * WPB + w;
+        int i0 = row_of(slot), i1 = row_of(slot + G), i2 = row_of(slot + 2 * G);
+        int64_t beg0 = a.ptr[i0 + z], end0 = a.ptr[i0 + 1 + z];
+        int64_t beg1 = a.ptr[i1 + z], end1 = a.ptr[i1 + 1 + z];
+        int col0 = 0;
+        float y0 = 0.f;
+        if (lane < min((int64_t)LDS::rows, end0 - beg0)) {
+            col0 = a.idx[beg0 + lane];
+            y0 = a.val ? a.val[beg0 + lane] : 0.f;
+        }
+        for (; slot < cnt; slot += G) {
+            const int64_t i = uni(i0), beg = uni64(beg0);
+            const int n = uni((int)(end0 - beg0));
+            const int colc = col0;
+            const float yc = y0;
+            // prefetch (each load depends only on values of the previous row)
+            col0 = 0;
+            y0 = 0.f;
+            if (lane < min((int64_t)LDS::rows, end1 - beg1)) {
+                col0 = a.idx[beg1 + lane];
+                y0 = a.val ? a.val[beg1 + lane] : 0.f;
+            }
+            beg0 = beg1;
+            end0 = end1;
+            beg1 = a.ptr[i2 + z];
+            end1 = a.ptr[i2 + 1 + z];
+            i0 = i1;
+            i1 = i2;
+            i2 = row_of(slot + 3 * G);
+            row(i, beg, n, lane, colc, yc);
+        }
+    } else {
+        // persistent launch: each wavefront takes the next row of the class from
+        // an atomic counter (rows are ordered by decreasing degree)
+        for (;;) {
+            unsigned int got = 0;
+            if (lane0 == 0) got = atomicAdd(a.queue, 1u);
+            const int64_t slot = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)got);
+            if (slot >= a.count) break;
+            const int lane = opaque_lane(lane0);
+            const int64_t i = a.perm[slot];
+            const int64_t beg = a.ptr[i];
+            row(i, beg, (int)(a.ptr[i + 1] - beg), lane, 0, 0.f);
+        }
     }
 }
 
 // Full-data light rows (LDL^T, no pivot search): fits two waves per SIMD as is.
-__global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL, false>(a); }
+__global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_rows<CLS_FULL, false, false>(a); }
 
 // Core light rows: the pivot search raises register demand; capping the
-// kernel at two waves per SIMD beats one wave per SIMD.
+// kernel at two waves per SIMD beats one wave per SIMD.  The smallest class
+// (rows of at most 19 entries at r = 1/10, solved in Woodbury form from one
+// 32-row chunk) is bound by fetching its rows: its rows are dealt out by wave
+// index with the next rows' indices prefetched.  The larger classes keep the
+// atomic queue, whose dynamic balance measured faster for them.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
-    sweep_rows<CLS, false>(a);
+    sweep_rows<CLS, false, CLS == CLS_NET1>(a);
 }
 
-// The two smallest classes (Woodbury form, 32-row LDS chunks): latency bound,
-// so more waves per SIMD; the registers of the rarely taken 64 x 64 fallback
-// spill instead.
+// The second Woodbury class (rows of 20 to 29 entries at r = 1/10): more
+// compute per row, so three waves per SIMD and the atomic row queue (the
+// prefetch state does not fit three waves without spilling the Woodbury
+// solve); the registers of the rarely taken 64 x 64 fallback spill instead.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAVES, WB_WAVES))) void k_sweep_wb(
     SweepArgs a) {
-    sweep_rows<CLS, false>(a);
+    sweep_rows<CLS, false, false>(a);
 }
 
 // Fold-in answers: residual check of the candidates, exact solve of the rest.
-__global__ __launch_bounds__(WPB * 64) void k_check_full(SweepArgs a) { sweep_rows<CLS_FULL, true>(a); }
+__global__ __launch_bounds__(WPB * 64) void k_check_full(SweepArgs a) { sweep_rows<CLS_FULL, true, false>(a); }
 
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_check_core(SweepArgs a) {
-    sweep_rows<CLS, true>(a);
+    sweep_rows<CLS, true, false>(a);
 }
 
 // CES positions for a contiguous row range (the core_select entry point).
@@ -214,6 +284,15 @@ __global__ __launch_bounds__(WPB * 64) void k_select(SelectArgs a) {
     }
 }
 
+// Workgroups of WPB waves of `kernel` that the device holds at once.
+int64_t resident_blocks(const void *kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, WPB * 64, 0) != hipSuccess) return 0;
+    return (int64_t)cus * per_cu;
+}
+
 template <int CLS, bool CHECK>
 hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
     int64_t blocks = (a.count + WPB - 1) / WPB;
@@ -227,10 +306,17 @@ hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
     } else {
         if constexpr (CLS == CLS_FULL)
             hipLaunchKernelGGL(k_sweep_full, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
-        else if constexpr (CLS == CLS_NET1 || CLS == CLS_NET2)
+        else if constexpr (CLS == CLS_NET2)
             hipLaunchKernelGGL(k_sweep_wb<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
-        else
+        else {
+            if constexpr (CLS == CLS_NET1) {
+                // rows are dealt out by wave index: the grid must be resident at once
+                const int64_t fit = resident_blocks(reinterpret_cast<const void *>(&k_sweep_core<CLS>));
+                if (fit <= 0) return hipErrorLaunchFailure;
+                if (blocks > fit) blocks = fit;
+            }
             hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+        }
     }
     return hipGetLastError();
 }
