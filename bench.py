@@ -317,7 +317,7 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
 
 # HIP kernel behind each timed group (group 8 is k_heavy_gram_bf16 in the BF16 modes)
 KERNEL_OF_GROUP = ["k_sweep_full"] + [f"k_sweep_core<{c}>" for c in range(1, 7)] + [
-    "k_heavy_select", "k_heavy_gram_f32", "k_heavy_solve", "k_heavy_resid", "k_heavy_refine"]
+    "k_heavy_select", "k_heavy_gram_x6", "k_heavy_solve", "k_heavy_resid", "k_heavy_refine"]
 
 TRAFFIC_FILE = os.path.join(ROOT, "paper_2509_18024_amd", "tuning", "hbm_traffic_gfx950.json")
 

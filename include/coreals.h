@@ -50,8 +50,10 @@ typedef enum {
 } als_status;
 
 typedef enum {
-    ALS_PREC_FP32 = 0,            /* FP32 Gram (heavy rows on FP32 MFMA tiles),
-                                     FP32 solve                               */
+    ALS_PREC_FP32 = 0,            /* FP32 Gram (heavy rows: FP32 products from
+                                     an exact three-way bf16 split on bf16
+                                     MFMA tiles, FP32 accumulation), FP32
+                                     solve                                    */
     ALS_PREC_BF16_IR = 1,         /* heavy rows: BF16 MFMA Gram (FP32 accumulate),
                                      FP32 LU, one refinement step with an FP32
                                      residual; light rows: FP32 Gram          */

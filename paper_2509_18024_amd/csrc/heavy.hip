@@ -14,16 +14,17 @@
 //                    only if more than HEAVY_CAP keys share it do two more
 //                    radix passes over the full keys run, and a position pass
 //                    where keys equal the threshold.
-//   k_heavy_gram_f32 one wavefront per (row, chunk of `chunk` entries) builds
+//   k_heavy_gram_x6  one wavefront per (row, chunk of `chunk` entries) builds
 //                    the chunk's part of X*^T X and X*^T y (eq. core_ui) with
-//                    the row's cut on 32x32x2 FP32 MFMA tiles, and stores it
-//                    to scratch (column-major: element (a, b) at b * 64 + a).
+//                    the row's cut, FP32 products from an exact three-way
+//                    bf16 split on 32x32x16 bf16 MFMA tiles, and stores it to
+//                    scratch (column-major: element (a, b) at b * 64 + a).
 //   k_heavy_solve    one wavefront per row sums its partial systems in chunk
 //                    order (deterministic), adds lambda n_i, and solves it
 //                    (pivoted LU).
 //
-// BF16 precision modes replace k_heavy_gram_f32 by k_heavy_gram_bf16 (the same
-// partial systems from bf16 MFMA tiles with FP32 accumulation) and add one
+// BF16 precision modes replace k_heavy_gram_x6 by k_heavy_gram_bf16 (the same
+// partial systems from plain bf16 roundings of the operands, FP32 accumulation) and add one
 // step of iterative refinement: k_heavy_resid forms the partial residuals
 // X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
 // second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the LU
@@ -650,24 +651,38 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64
     }
 }
 
-// FP32 Gram of a (row, chunk) pair on 32x32x2 FP32 MFMA tiles (exact FP32
-// products, FP32 accumulation): accurate enough that no refinement step is
-// needed.  Operands come straight from memory: for entries (k, k + 1) lane
-// (m, h) loads columns m and 32 + m of factor row idx[k + h] (two 128-byte
-// segments per load instruction), which is exactly its A and B operand slot;
-// A = X*^T (masked by the row's cut), B = X.  Column indices and ratings of a
-// 64-entry block are parked in LDS so that each lane reads its own with one
-// LDS load; the cut test is one 64-bit compare of (key, -position).  Entries
-// past the chunk and padded columns (a >= n_f) read zeros: their buffer
-// offsets lie beyond the factor matrix, where buffer loads return 0.
-constexpr int GF_PAIRS = 16;               // entry pairs gathered per batch
-constexpr uint32_t GF_NONE = 0x80000000u;  // an offset past any factor matrix
+constexpr uint32_t GF_NONE = 0x80000000u;  // a buffer offset past any factor matrix
 
-// BUF: buffer loads with 32-bit offsets and the zero padding of out-of-range
-// offsets (factor matrices below 2^24 rows and 2^31 bytes); else 64-bit
-// addresses, clamped rows and explicit zeros.
+// Partial system of a (row, chunk) pair, A = X*^T X and b = X*^T y over the
+// chunk's entries, on bf16 MFMA tiles with FP32 accuracy.  Each operand value
+// splits exactly as x = h + m + l: h is x with its low 16 bits cleared, m is
+// x - h with its low 16 bits cleared, l = x - h - m; all three are bfloat16
+// numbers (h is the upper half of x's bits, and the 24 significant bits of x
+// leave at most 8 for each part).  The product x x' is h h' + h m' + m h' +
+// m m' + h l' + l h' up to terms below 2^-22 |x x'|, and bf16 products are
+// exact in FP32, so six 32x32x16 bf16 MFMAs per tile and 16 entries (together
+// 3/8 of the matrix-core time of the eight 32x32x2 FP32 MFMAs they replace)
+// give FP32 products with FP32 accumulation; no refinement step is needed.
+// A = X*^T (masked by the row's cut), B = X.  Lane (i, h) holds entries
+// 8h .. 8h + 7 of a 16-entry step for column i of its tile, which is its slot
+// in both the A operand (32 x 16) and the B operand (16 x 32); it loads them
+// straight from memory (columns i and 32 + i of each entry's factor row: two
+// 128-byte segments per load instruction).  Column indices and ratings of a
+// 64-entry block are parked in LDS so that each lane reads its own with one LDS
+// load; the cut test is one 64-bit compare of (key, -position).  Entries past
+// the chunk and padded columns (a >= n_f) read zeros: with BUF their buffer
+// offsets lie beyond the factor matrix, where buffer loads return 0.
+// BUF: buffer loads with 32-bit offsets (factor matrices below 2^24 rows and
+// 2^31 bytes); else 64-bit addresses, clamped rows and explicit zeros.
+constexpr int GX_STEPS = 1;  // 16-entry MFMA steps per gather batch
+
+__device__ __forceinline__ uint32_t hi_halves(uint32_t lo_entry, uint32_t hi_entry) {
+    // (upper 16 bits of hi_entry) << 16 | (upper 16 bits of lo_entry)
+    return __builtin_amdgcn_perm(hi_entry, lo_entry, 0x07060302u);
+}
+
 template <bool BUF>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_heavy_gram_f32(
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_x6(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
     __shared__ float s_y[WPB][64];
@@ -706,14 +721,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))
         }
         const uint64_t b0 = ((uint64_t)(uint32_t)T0 << 32) | (uint32_t)~K0;
         const uint64_t b1 = ((uint64_t)(uint32_t)T1 << 32) | (uint32_t)~K1;
-        f32x16 acc00, acc01, acc10, acc11;
+        f32x16 acc[2][2];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc00[q] = acc01[q] = acc10[q] = acc11[q] = 0.f;
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[ta][tb][q] = 0.f;
         float racc0 = 0.f, racc1 = 0.f;
         const int kb = chunk * a.chunk;
         const int ke = min(n, kb + a.chunk);
-        // lane j of colv / yv: entry k0 + j of the block, column `rows` and
-        // rating 0 past the chunk; the next block's load while this one is used
         int colv = kb + lane < ke ? a.idx[beg + kb + lane] : rows;
         float yv = kb + lane < ke ? a.val[beg + kb + lane] : 0.f;
         for (int k0 = kb; k0 < ke; k0 += 64) {
@@ -729,57 +746,108 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4, 4))
                 yv = k1 + lane < ke ? a.val[beg + k1 + lane] : 0.f;
             }
 #pragma unroll 1
-            for (int e0 = k0; e0 < min(ke, k1); e0 += 2 * GF_PAIRS) {
+            for (int e0 = k0; e0 < min(ke, k1); e0 += 16 * GX_STEPS) {
                 const int j0 = e0 - k0;
-                float x0[GF_PAIRS], x1[GF_PAIRS];
+                float x0[GX_STEPS][8], x1[GX_STEPS][8];
 #pragma unroll
-                for (int q = 0; q < GF_PAIRS; ++q) {
-                    const int col = s_col[w][j0 + 2 * q + h];
-                    if constexpr (BUF) {
-                        const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
-                        x0[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
-                        x1[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
-                    } else {
-                        const size_t ro = (size_t)max(col, 0) * nf;
-                        const float u0 = col0p[ro], u1 = col1p[ro];
-                        x0[q] = (col >= 0 && live0) ? u0 : 0.f;
-                        x1[q] = (col >= 0 && live1) ? u1 : 0.f;
+                for (int st = 0; st < GX_STEPS; ++st)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int col = s_col[w][j0 + 16 * st + 8 * h + e];
+                        if constexpr (BUF) {
+                            const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
+                            x0[st][e] =
+                                __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off0), 0, 0));
+                            x1[st][e] =
+                                __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + off1), 0, 0));
+                        } else {
+                            const size_t ro = (size_t)max(col, 0) * nf;
+                            const float u0 = col0p[ro], u1 = col1p[ro];
+                            x0[st][e] = (col >= 0 && live0) ? u0 : 0.f;
+                            x1[st][e] = (col >= 0 && live1) ? u1 : 0.f;
+                        }
                     }
-                }
                 // every gather of the batch is issued before the first use
                 __builtin_amdgcn_sched_barrier(0);
-                const uint32_t nk0 = ~(uint32_t)(e0 + h);  // ~k of pair 0
 #pragma unroll
-                for (int q = 0; q < GF_PAIRS; ++q) {
-                    const float v0 = x0[q], v1 = x1[q];
-                    const uint32_t nk = nk0 - 2u * q;
-                    const uint64_t a0 = ((uint64_t)(__float_as_uint(v0) & 0x7FFFFFFFu) << 32) | nk;
-                    const uint64_t a1 = ((uint64_t)(__float_as_uint(v1) & 0x7FFFFFFFu) << 32) | nk;
-                    const float w0 = a0 >= b0 ? v0 : 0.f;
-                    const float w1 = a1 >= b1 ? v1 : 0.f;
-                    const float y = s_y[w][j0 + 2 * q + h];
-                    racc0 = fmaf(w0, y, racc0);
-                    racc1 = fmaf(w1, y, racc1);
-                    acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v0, acc00, 0, 0, 0);
-                    acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(w0, v1, acc01, 0, 0, 0);
-                    acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v0, acc10, 0, 0, 0);
-                    acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(w1, v1, acc11, 0, 0, 0);
+                for (int st = 0; st < GX_STEPS; ++st) {
+                    const uint32_t nkb = ~(uint32_t)(e0 + 16 * st + 8 * h);  // ~k of the lane's first entry
+                    uint32_t ph[2][4], pm[2][4], pl[2][4], mk[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const uint64_t bt = t ? b1 : b0;
+#pragma unroll
+                        for (int e2 = 0; e2 < 4; ++e2) {
+                            uint32_t uh[2], um[2], ul[2], km[2];
+#pragma unroll
+                            for (int o = 0; o < 2; ++o) {
+                                const int e = 2 * e2 + o;
+                                const float x = t ? x1[st][e] : x0[st][e];
+                                const uint32_t u = __float_as_uint(x);
+                                const float r1 = x - __uint_as_float(u & 0xFFFF0000u);
+                                const uint32_t v = __float_as_uint(r1);
+                                const float r2 = r1 - __uint_as_float(v & 0xFFFF0000u);
+                                uh[o] = u;
+                                um[o] = v;
+                                ul[o] = __float_as_uint(r2);
+                                const uint64_t key = ((uint64_t)(u & 0x7FFFFFFFu) << 32) | (nkb - (uint32_t)e);
+                                const bool kp = key >= bt;
+                                km[o] = kp ? 0xFFFFu : 0u;
+                                const float y = s_y[w][j0 + 16 * st + 8 * h + e];
+                                if (t) racc1 = fmaf(kp ? x : 0.f, y, racc1);
+                                else racc0 = fmaf(kp ? x : 0.f, y, racc0);
+                            }
+                            ph[t][e2] = hi_halves(uh[0], uh[1]);
+                            pm[t][e2] = hi_halves(um[0], um[1]);
+                            pl[t][e2] = hi_halves(ul[0], ul[1]);
+                            mk[t][e2] = km[0] | (km[1] << 16);
+                        }
+                    }
+                    // B operands (all entries) and A operands (kept entries only)
+                    bf16x8 bh[2], bm[2], bl[2], ah[2], am[2], al[2];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        uint32_t qh[4], qm[4], ql[4];
+#pragma unroll
+                        for (int e2 = 0; e2 < 4; ++e2) {
+                            qh[e2] = ph[t][e2] & mk[t][e2];
+                            qm[e2] = pm[t][e2] & mk[t][e2];
+                            ql[e2] = pl[t][e2] & mk[t][e2];
+                        }
+                        bh[t] = __builtin_bit_cast(bf16x8, ph[t]);
+                        bm[t] = __builtin_bit_cast(bf16x8, pm[t]);
+                        bl[t] = __builtin_bit_cast(bf16x8, pl[t]);
+                        ah[t] = __builtin_bit_cast(bf16x8, qh);
+                        am[t] = __builtin_bit_cast(bf16x8, qm);
+                        al[t] = __builtin_bit_cast(bf16x8, ql);
+                    }
+                    // six products per tile, the four tiles interleaved so that
+                    // consecutive MFMAs are independent
+#define GX_MFMA(A, B)                                                                             \
+    _Pragma("unroll") for (int ta = 0; ta < 2; ++ta) _Pragma("unroll") for (int tb = 0; tb < 2; ++tb) \
+        acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[ta], B[tb], acc[ta][tb], 0, 0, 0);
+                    GX_MFMA(al, bh)
+                    GX_MFMA(ah, bl)
+                    GX_MFMA(am, bm)
+                    GX_MFMA(am, bh)
+                    GX_MFMA(ah, bm)
+                    GX_MFMA(ah, bh)
+#undef GX_MFMA
                 }
             }
         }
         racc0 += __shfl_xor(racc0, 32);
         racc1 += __shfl_xor(racc1, 32);
-        // D[i][j] of tile (ta, tb) = A[32 ta + i][32 tb + j], stored at
-        // dst[(32 tb + j) * 64 + 32 ta + i], the layout k_heavy_solve reads
         float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int row = 8 * (q >> 2) + 4 * h + (q & 3);
-            dst[m * 64 + row] = acc00[q];
-            dst[(32 + m) * 64 + row] = acc01[q];
-            dst[m * 64 + 32 + row] = acc10[q];
-            dst[(32 + m) * 64 + 32 + row] = acc11[q];
-        }
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = 8 * (q >> 2) + 4 * h + (q & 3);
+                    dst[(32 * tb + m) * 64 + 32 * ta + row] = acc[ta][tb][q];
+                }
         if (h == 0) {
             dst[NF * 64 + m] = racc0;
             dst[NF * 64 + 32 + m] = racc1;
@@ -1004,8 +1072,8 @@ hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pai
     const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
                      a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
     const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
-    if (buf) hipLaunchKernelGGL(k_heavy_gram_f32<true>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
-    else hipLaunchKernelGGL(k_heavy_gram_f32<false>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    if (buf) hipLaunchKernelGGL(k_heavy_gram_x6<true>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else hipLaunchKernelGGL(k_heavy_gram_x6<false>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
     return hipGetLastError();
 }
 
