@@ -658,11 +658,12 @@ constexpr uint32_t GF_NONE = 0x80000000u;  // a buffer offset past any factor ma
 // splits exactly as x = h + m + l: h is x with its low 16 bits cleared, m is
 // x - h with its low 16 bits cleared, l = x - h - m; all three are bfloat16
 // numbers (h is the upper half of x's bits, and the 24 significant bits of x
-// leave at most 8 for each part).  The product x x' is h h' + h m' + m h' +
-// m m' + h l' + l h' up to terms below 2^-22 |x x'|, and bf16 products are
-// exact in FP32, so six 32x32x16 bf16 MFMAs per tile and 16 entries (together
-// 3/8 of the matrix-core time of the eight 32x32x2 FP32 MFMAs they replace)
-// give FP32 products with FP32 accumulation; no refinement step is needed.
+// leave at most 8 for each part; |m| < 2^-7 |x|, |l| < 2^-14 |x|).  The
+// product x x' is h h' + h m' + m h' + m m' + h l' + l h' up to terms below
+// 2^-20 |x x'|, and bf16 products are exact in FP32, so six 32x32x16 bf16
+// MFMAs per tile and 16 entries (together 3/8 of the matrix-core time of the
+// eight 32x32x2 FP32 MFMAs they replace) give products within a few FP32
+// roundings, accumulated in FP32; no refinement step is needed.
 // A = X*^T (masked by the row's cut), B = X.  Lane (i, h) holds entries
 // 8h .. 8h + 7 of a 16-entry step for column i of its tile, which is its slot
 // in both the A operand (32 x 16) and the B operand (16 x 32); it loads them
