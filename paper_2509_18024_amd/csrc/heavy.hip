@@ -655,15 +655,16 @@ constexpr uint32_t GF_NONE = 0x80000000u;  // a buffer offset past any factor ma
 
 // Partial system of a (row, chunk) pair, A = X*^T X and b = X*^T y over the
 // chunk's entries, on bf16 MFMA tiles with FP32 accuracy.  Each operand value
-// splits exactly as x = h + m + l: h is x with its low 16 bits cleared, m is
-// x - h with its low 16 bits cleared, l = x - h - m; all three are bfloat16
-// numbers (h is the upper half of x's bits, and the 24 significant bits of x
-// leave at most 8 for each part; |m| < 2^-7 |x|, |l| < 2^-14 |x|).  The
-// product x x' is h h' + h m' + m h' + m m' + h l' + l h' up to terms below
-// 2^-20 |x x'|, and bf16 products are exact in FP32, so six 32x32x16 bf16
-// MFMAs per tile and 16 entries (together 3/8 of the matrix-core time of the
-// eight 32x32x2 FP32 MFMAs they replace) give products within a few FP32
-// roundings, accumulated in FP32; no refinement step is needed.
+// splits exactly as x = h + m + l: h is x rounded to nearest bfloat16, m is
+// x - h (exact in FP32) rounded to nearest, l = x - h - m, itself a bfloat16
+// number (the 24 significant bits of x leave at most 8 for it); |m| <=
+// 2^-8 |x|, |l| <= 2^-16 |x|.  The product x x' is h h' + h m' + m h' + m m' +
+// h l' + l h' up to terms below 2^-23 |x x'| of either sign, and bf16 products
+// are exact in FP32, so six 32x32x16 bf16 MFMAs per tile and 16 entries
+// (together 3/8 of the matrix-core time of the eight 32x32x2 FP32 MFMAs they
+// replace) give FP32 products with FP32 accumulation; no refinement step is
+// needed.  (Truncated parts would drop terms up to 2^-20 |x x'|, all of one
+// sign on the diagonal: a bias that long rows accumulate.)
 // A = X*^T (masked by the row's cut), B = X.  Lane (i, h) holds entries
 // 8h .. 8h + 7 of a 16-entry step for column i of its tile, which is its slot
 // in both the A operand (32 x 16) and the B operand (16 x 32); it loads them
@@ -677,9 +678,13 @@ constexpr uint32_t GF_NONE = 0x80000000u;  // a buffer offset past any factor ma
 // 2^31 bytes); else 64-bit addresses, clamped rows and explicit zeros.
 constexpr int GX_STEPS = 1;  // 16-entry MFMA steps per gather batch
 
-__device__ __forceinline__ uint32_t hi_halves(uint32_t lo_entry, uint32_t hi_entry) {
-    // (upper 16 bits of hi_entry) << 16 | (upper 16 bits of lo_entry)
-    return __builtin_amdgcn_perm(hi_entry, lo_entry, 0x07060302u);
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// Two values rounded to nearest bfloat16 (one v_cvt_pk_bf16_f32), packed with
+// the first in the low half.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 template <bool BUF>
@@ -779,18 +784,14 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                         const uint64_t bt = t ? b1 : b0;
 #pragma unroll
                         for (int e2 = 0; e2 < 4; ++e2) {
-                            uint32_t uh[2], um[2], ul[2], km[2];
+                            float xv[2];
+                            uint32_t km[2];
 #pragma unroll
                             for (int o = 0; o < 2; ++o) {
                                 const int e = 2 * e2 + o;
                                 const float x = t ? x1[st][e] : x0[st][e];
+                                xv[o] = x;
                                 const uint32_t u = __float_as_uint(x);
-                                const float r1 = x - __uint_as_float(u & 0xFFFF0000u);
-                                const uint32_t v = __float_as_uint(r1);
-                                const float r2 = r1 - __uint_as_float(v & 0xFFFF0000u);
-                                uh[o] = u;
-                                um[o] = v;
-                                ul[o] = __float_as_uint(r2);
                                 const uint64_t key = ((uint64_t)(u & 0x7FFFFFFFu) << 32) | (nkb - (uint32_t)e);
                                 const bool kp = key >= bt;
                                 km[o] = kp ? 0xFFFFu : 0u;
@@ -798,9 +799,17 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                                 if (t) racc1 = fmaf(kp ? x : 0.f, y, racc1);
                                 else racc0 = fmaf(kp ? x : 0.f, y, racc0);
                             }
-                            ph[t][e2] = hi_halves(uh[0], uh[1]);
-                            pm[t][e2] = hi_halves(um[0], um[1]);
-                            pl[t][e2] = hi_halves(ul[0], ul[1]);
+                            // x = h + m + l, each part rounded to nearest from
+                            // the exact remainder of the previous ones
+                            const uint32_t qh = pack_bf16(xv[0], xv[1]);
+                            const float r0 = xv[0] - __uint_as_float(qh << 16);
+                            const float r1 = xv[1] - __uint_as_float(qh & 0xFFFF0000u);
+                            const uint32_t qm = pack_bf16(r0, r1);
+                            const float s0 = r0 - __uint_as_float(qm << 16);
+                            const float s1 = r1 - __uint_as_float(qm & 0xFFFF0000u);
+                            ph[t][e2] = qh;
+                            pm[t][e2] = qm;
+                            pl[t][e2] = pack_bf16(s0, s1);
                             mk[t][e2] = km[0] | (km[1] << 16);
                         }
                     }
