@@ -438,6 +438,42 @@ def test_wide_row_selection_and_sweep(ora):
 
 
 @gpu
+@pytest.mark.parametrize("n_u,deg_lo,deg_hi,light_blocks", [(3000, 2, 40, 0), (37, 2, 40, 0), (500, 20, 40, 2)])
+def test_strided_smallest_class(ora, n_u, deg_lo, deg_hi, light_blocks):
+    """Rows of the smallest class (s_i = 1) at r = 1/20, dealt out by wave
+    index with prefetched indices: rows of up to 32 entries solve in Woodbury
+    form from the prefetched chunk; rows of 33 to 39 entries take the 64 x 64
+    path, whose second 32-row chunk is staged from memory.  Also a class with
+    fewer rows than waves, and a grid of 2 workgroups (8 waves) for 500 rows."""
+    import torch
+    from paper_2509_18024_amd import capi
+    rng = np.random.default_rng(n_u + deg_hi)
+    n_m, nf = 900, 64
+    deg = rng.integers(deg_lo, deg_hi, n_u)
+    rows = [np.sort(rng.choice(n_m, d, replace=False)) for d in deg]
+    rp = np.zeros(n_u + 1, np.int64)
+    np.cumsum(deg, out=rp[1:])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(len(ci)).astype(np.float32)
+    M0 = (0.1 * rng.standard_normal((n_m, nf))).astype(np.float32)
+    p = synth.Problem("strided", n_u, n_m, nf, rp, ci, val, 0.05, 1, 20, 1, 1, M0)
+    note(f"[strided smallest class] n_u={n_u} degrees {deg_lo}..{deg_hi - 1} light_blocks={light_blocks}")
+    als = make_als(p, light_blocks=light_blocks)
+    counts = capi.als_class_counts(als.ctx)
+    note(f"  classes users {counts[0]}")
+    assert counts[0][1] > 0
+    U = als.half_sweep_users(torch.from_numpy(M0).cuda())
+    torch.cuda.synchronize()
+    Uo, _ = ora.half_sweep(rp, ci, val, M0.astype(np.float64), 0.05, 1, 20, 1)
+    err = rel_fro(U.cpu().numpy(), Uo)
+    long_rows = deg > 32
+    err_long = rel_fro(U.cpu().numpy()[long_rows], Uo[long_rows]) if long_rows.any() else 0.0
+    note(f"  rel err {err:.2e} (rows of 33+ entries: {err_long:.2e}, {int(long_rows.sum())} rows)")
+    assert err <= 1e-4 and err_long <= 1e-4
+    als.close()
+
+
+@gpu
 @pytest.mark.parametrize("budget,scale", [((1, 10), 0.1), ((1, 20), 0.08), ((1, 10), 0.35), ((1, 10), 0.45)])
 def test_small_rows_woodbury_form(ora, budget, scale):
     """Rows of the two smallest network classes (n <= 32): their n x n Woodbury
