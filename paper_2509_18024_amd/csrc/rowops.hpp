@@ -423,18 +423,27 @@ __device__ __forceinline__ void finish_system(float (&A)[NF], float &rhs, float 
 // reaches the other lanes through scalar broadcasts (v_readlane).
 // KEEP: the multiplier of each eliminated row is stored in its column J (no
 // longer needed there), so that the factors can solve later right-hand sides.
+// The pivot candidate of column J for the lane's row: its magnitude with the
+// low 6 bits replaced by 63 - lane, so that one maximum gives the pivot lane
+// (the first of equal candidates; magnitudes within 2^-17 of each other count
+// as equal); -1 for rows already used as pivots.
+template <int J>
+__device__ __forceinline__ int pivot_key(const float (&A)[NF], int lane, int my_step) {
+    const int cand = my_step == NF ? ((__float_as_int(fabsf(A[J])) & ~63) | (63 - lane)) : -1;
+    return wave_max_key(cand);
+}
+
+// pk: with PIVOT, the wave's maximum pivot key of column J, computed by the
+// previous step as soon as column J was final (lookahead: the reduction runs
+// beside the rest of that step's update); on return, the key of column J + 1.
 template <bool PIVOT, int NR, int J, bool KEEP>
 __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
-                                            int &my_step, bool &ok) {
+                                            int &my_step, bool &ok, int &pk) {
     int p;
     bool active;
     if constexpr (PIVOT) {
-        // the candidate's magnitude with its low 6 bits replaced by 63 - lane:
-        // one maximum gives the pivot lane (the first of equal candidates;
-        // magnitudes within 2^-17 of each other count as equal)
         active = my_step == NF;
-        const int cand = active ? ((__float_as_int(fabsf(A[J])) & ~63) | (63 - lane)) : -1;
-        p = 63 - (wave_max_key(cand) & 63);
+        p = 63 - (pk & 63);
     } else {
         active = lane >= J;
         p = J;
@@ -459,6 +468,8 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
 #pragma unroll
         for (int t = 0; t < 8; ++t)
             if (c0 + t < NF) A[c0 + t] = fmaf(-l, pr[t], A[c0 + t]);
+        if constexpr (PIVOT && J + 1 < NF)
+            if (c0 == J + 1) pk = pivot_key<J + 1>(A, lane, my_step);  // column J + 1 is final
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) rhs[q] = fmaf(-l, readlane_f(rhs[q], p), rhs[q]);
@@ -488,7 +499,8 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
 template <bool PIVOT, int NR, bool KEEP, int... J>
 __device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR],
                                            int lane, int nf, float tol, int &my_step, bool &ok) {
-    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok), ...);
+    int pk = PIVOT ? pivot_key<0>(A, lane, my_step) : 0;
+    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok, pk), ...);
 }
 
 // Forward elimination of a new right-hand side with kept factors: at step J
@@ -583,12 +595,20 @@ constexpr int WB_D = 32;
 constexpr float WB_AMP = 256.f;
 
 template <int J>
+__device__ __forceinline__ int wb_pivot_key(const float (&G)[WB_D], int lane, int my_step) {
+    // as pivot_key
+    const int cand = my_step == WB_D + 1 ? ((__float_as_int(fabsf(G[J])) & ~63) | (63 - lane)) : -1;
+    return wave_max_key(cand);
+}
+
+// pk: the pivot key of column J, computed by the previous step (lookahead as
+// in elim_step_u); on return, that of column J + 1.
+template <int J>
 __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lane, int n, float tol, int &my_step,
-                                             bool &ok) {
+                                             bool &ok, int &pk) {
     if (J >= n) return;  // uniform: the system has n rows
     const bool active = my_step == WB_D + 1;
-    const int cand = active ? ((__float_as_int(fabsf(G[J])) & ~63) | (63 - lane)) : -1;  // as in elim_step_u
-    const int p = 63 - (wave_max_key(cand) & 63);
+    const int p = 63 - (pk & 63);
     const float piv = readlane_f(G[J], p);
     ok = ok && fabsf(piv) > tol;
     const bool elim = active && lane != p;
@@ -605,6 +625,8 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (c0 + k < WB_D) G[c0 + k] = fmaf(-l, pr[k], G[c0 + k]);
+        if constexpr (J + 1 < WB_D)
+            if (c0 == J + 1) pk = wb_pivot_key<J + 1>(G, lane, my_step);  // column J + 1 is final (J + 1 < n)
     }
     t = fmaf(-l, readlane_f(t, p), t);
 }
@@ -627,7 +649,8 @@ __device__ __forceinline__ bool wb_lu(std::integer_sequence<int, J...>, float (&
                                       float tol, float *zs) {
     int my_step = WB_D + 1;
     bool ok = true;
-    (wb_elim_step<J>(G, t, lane, n, tol, my_step, ok), ...);
+    int pk = wb_pivot_key<0>(G, lane, my_step);
+    (wb_elim_step<J>(G, t, lane, n, tol, my_step, ok, pk), ...);
     if (!ok) return false;
     (wb_back_step<WB_D - 1 - J>(G, t, lane, n, my_step, zs), ...);
     return true;
