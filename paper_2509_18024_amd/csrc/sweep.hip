@@ -138,11 +138,12 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
 
     if constexpr (STRIDED) {
         // Wave g takes rows g, g + G, g + 2G, ... of the class (G waves in the
-        // grid, all resident; rows of similar degree, so the shares balance),
-        // which lets the row bounds and indices of the next rows load while
-        // this one is solved: with two waves per SIMD the fetch latency of a
-        // row is otherwise exposed.  Pipeline: indices of row t + 1, bounds of
-        // row t + 2 and the row number of row t + 3 are fetched during row t.
+        // grid, all resident; rows of similar degree, so the shares balance).
+        // No row counter: for rows this small a single atomic counter limits
+        // the class by its throughput.  And the next rows are known, so their
+        // bounds and indices load while this one is solved.  Pipeline: indices
+        // of row t + 1, bounds of row t + 2 and the row number of row t + 3 are
+        // fetched during row t.
         const int64_t G = (int64_t)gridDim.x * WPB;
         const int64_t cnt = a.count;
         const int lane = opaque_lane(lane0);
@@ -211,9 +212,10 @@ __global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_ro
 // Core light rows: the pivot search raises register demand; capping the
 // kernel at two waves per SIMD beats one wave per SIMD.  The smallest class
 // (rows of at most 19 entries at r = 1/10, solved in Woodbury form from one
-// 32-row chunk) is bound by fetching its rows: its rows are dealt out by wave
-// index with the next rows' indices prefetched.  The larger classes keep the
-// atomic queue, whose dynamic balance measured faster for them.
+// 32-row chunk) claims rows faster than one atomic counter serves them: its
+// rows are dealt out by wave index, with the next rows' indices prefetched.
+// The larger classes keep the atomic queue, whose dynamic balance measured
+// faster for them.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
     sweep_rows<CLS, false, CLS == CLS_NET1>(a);
