@@ -63,14 +63,14 @@ typedef enum {
 } als_precision;
 
 #define ALS_VALIDATE 1u   /* check ratings for NaN/Inf in als_init */
-#define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
-                                 even where 32-bit buffer offsets would do (the
-                                 path taken for factor matrices of 2^24 rows or
-                                 2^31 bytes and more; slower, for tests) */
 #define ALS_USERS_ONLY 2u /* users side only: no column view is built, and
                              half_sweep_items, core_select(side 1) and objective
                              return ALS_E_STATE (contexts of new users to fold
                              in, see foldin_answer) */
+#define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
+                                 even where 32-bit buffer offsets would do (the
+                                 path taken for factor matrices of 2^24 rows or
+                                 2^31 bytes and more; slower, for tests) */
 
 typedef struct {
     int64_t n_u, n_m, nnz;

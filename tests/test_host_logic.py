@@ -50,3 +50,26 @@ def test_c3_small_scale_shape():
     p = synth.c3_batched(scale=0.002)
     d = np.diff(p.row_ptr)
     assert p.n_f == 64 and d.min() >= 1 and p.nnz > 0.8e8 * 0.002
+
+
+def test_binding_constants_match_the_header():
+    """The ctypes binding repeats the C header's enum values and flag bits; a
+    mismatch would pass wrong flags or misread status codes."""
+    import os
+    import re
+    from paper_2509_18024_amd import capi
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "include", "coreals.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    defines = dict((k, int(v)) for k, v in re.findall(r"#define\s+(ALS_\w+)\s+(\d+)u?\b", text))
+    enums = dict((k, int(v)) for k, v in re.findall(r"\b(ALS_\w+|FOLDIN_\w+)\s*=\s*(\d+)", text))
+    assert {"ALS_VALIDATE", "ALS_USERS_ONLY", "ALS_GENERIC_GATHERS"} <= set(defines)
+    assert {"ALS_OK", "ALS_E_STATE", "ALS_PREC_FP32", "ALS_PREC_AUTO"} <= set(enums)
+    flags = [defines[k] for k in ("ALS_VALIDATE", "ALS_USERS_ONLY", "ALS_GENERIC_GATHERS")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)  # distinct bits
+    for name, value in {**defines, **enums}.items():
+        if hasattr(capi, name):
+            assert getattr(capi, name) == value, name
+    for name in ("ALS_VALIDATE", "ALS_USERS_ONLY", "ALS_GENERIC_GATHERS", "ALS_OK", "ALS_E_ARG",
+                 "ALS_E_STATE", "ALS_PREC_FP32", "ALS_PREC_BF16_IR", "ALS_PREC_AUTO"):
+        assert hasattr(capi, name), name
