@@ -361,7 +361,9 @@ def heavy_cases():
     p1 = synth.random_problem(12, 120, 700, 64, 0.3, budget=(1, 4), heavy_rows=(0, 5, 9))
     p2 = synth.random_problem(13, 400, 90, 16, 0.35, budget=(1, 1), heavy_rows=(1,))
     p3 = synth.random_problem(14, 600, 200, 64, 0.25, budget=(1, 10), min_keep=0, heavy_rows=(2, 3))
-    return [("heavy_r1/4", p1), ("heavy_full_nf16", p2), ("heavy_r1/10_minkeep0", p3)]
+    # n_f = 48: the second 32-column tile of the heavy-row Gram is partly padding
+    p4 = synth.random_problem(16, 300, 260, 48, 0.3, budget=(1, 10), heavy_rows=(0, 4))
+    return [("heavy_r1/4", p1), ("heavy_full_nf16", p2), ("heavy_r1/10_minkeep0", p3), ("heavy_r1/10_nf48", p4)]
 
 
 HEAVY_KW = dict(heavy_min_degree=64, heavy_chunk=32, heavy_pair_cap=64)
@@ -369,7 +371,7 @@ HEAVY_KW = dict(heavy_min_degree=64, heavy_chunk=32, heavy_pair_cap=64)
 
 @gpu
 @pytest.mark.parametrize("generic", [False, True])
-@pytest.mark.parametrize("which", range(3))
+@pytest.mark.parametrize("which", range(4))
 def test_heavy_rows_match_oracle(ora, which, generic):
     """generic: the heavy-row selection and Gram gather with 64-bit addresses,
     the path of factor matrices too large for 32-bit buffer offsets."""
