@@ -539,7 +539,7 @@ def test_heavy_selection_full_radix_with_ties(ora, generic):
 
 @gpu
 @pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("which", range(3))
+@pytest.mark.parametrize("which", range(4))
 def test_bf16_refined_heavy_rows(ora, which, prec):
     """BF16 MFMA Gram on heavy rows + one refinement step (FP32 or FP64
     residual) against the FP64 oracle.  Parity with the oracle is not fixed by
