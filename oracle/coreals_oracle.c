@@ -22,9 +22,11 @@
  *  - ties in the top-s are broken by smaller position first;
  *  - s = min(n, max(min_keep, floor(n num / den))) in 64-bit integers;
  *  - an empty row gets the zero vector (counted);
- *  - a core system whose partial-pivoting LU meets a pivot with
+ *  - a core system (s < n) whose partial-pivoting LU meets a pivot with
  *    |pivot| <= n_f 2^-52 max|A| is replaced by the full-data row update
- *    (eq. (U)), solved by Cholesky (counted as a singular fallback).
+ *    (eq. (U)), solved by Cholesky (counted as a singular fallback); when
+ *    s = n the system already is eq. (U), and a singular one gives u = 0
+ *    (not counted).
  *
  * All arithmetic is double precision.  Input factor matrices are double
  * (callers widen fp32 arrays exactly).  OpenMP parallelises over rows only;
@@ -224,7 +226,9 @@ static int ora_full_row(int64_t n, int32_t nf, const double *X, const double *y,
 }
 
 /* One core regression, eq. core_ui: X is n x nf, y has n entries.
- * Returns 0 normal, 1 empty row, 2 singular fallback taken. */
+ * Returns 0 normal, 1 empty row, 2 singular fallback taken (core rows, s < n),
+ * 3 singular full-data system (s = n: the system is eq. (U) itself, so there
+ * is nothing to fall back to; u = 0). */
 int ora_core_row(int64_t n, int32_t nf, const double *X, const double *y, double lam,
                  int64_t s, double *u) {
     if (n == 0) {
@@ -250,8 +254,13 @@ int ora_core_row(int64_t n, int32_t nf, const double *X, const double *y, double
     double tol = (double)nf * ldexp(1.0, -52) * amax;
     int status = 0;
     if (ora_gepp(nf, A, b, tol)) {
-        ora_full_row(n, nf, X, y, lam, u);
-        status = 2;
+        if (s < n) {
+            ora_full_row(n, nf, X, y, lam, u);
+            status = 2;
+        } else {
+            for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+            status = 3;
+        }
     } else {
         for (int32_t a = 0; a < nf; ++a) u[a] = b[a];
     }

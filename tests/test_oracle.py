@@ -280,3 +280,104 @@ def test_theorem1_bound_diagnostic(ora):
         rhs = (1 + eps) * np.linalg.norm(y - X @ u_full) ** 2
         viol += lhs > rhs
     print(f"theorem-1 diagnostic: {viol} violations out of {tried} admissible draws")
+
+
+def _csr_from_rows(rows_list):
+    rp = np.zeros(len(rows_list) + 1, np.int64)
+    np.cumsum([len(r) for r in rows_list], out=rp[1:])
+    ci = np.concatenate([np.asarray(r, np.int64) for r in rows_list] + [np.zeros(0, np.int64)])
+    return rp, ci.astype(np.int32)
+
+
+def _pin_rows_problem(seed=41):
+    """Rows of mixed degree over 1500 items: an empty row, rows of 1..9 entries
+    (s = 0 at min_keep = 0), mid rows, and one row of 1300 entries (above the
+    GPU's light-row limit); factor values on a coarse grid so that ties occur."""
+    rng = np.random.default_rng(seed)
+    n_m, nf = 1500, 6
+    degs = [0, 1, 3, 9, 10, 11, 40, 97, 1300, 250, 0, 64]
+    rows = [np.sort(rng.choice(n_m, d, replace=False)) for d in degs]
+    rp, ci = _csr_from_rows(rows)
+    val = rng.standard_normal(len(ci)).astype(np.float32)
+    M = (np.round(rng.standard_normal((n_m, nf)) * 8.0) / 8.0).astype(np.float32)
+    return rp, ci, val, M
+
+
+@pytest.mark.parametrize("num,den,min_keep", [(1, 10, 1), (1, 10, 0), (3, 10, 2), (1, 1, 1)])
+def test_core_select_rows_pinned_by_bruteforce(ora, num, den, min_keep):
+    """core_select_rows on a permuted, non-contiguous row list (with a repeat):
+    sel_ptr are the prefix sums of n_f s_i written out here, and each row's
+    block holds, per column, the positions of a lexicographic (-|x|, position)
+    sort of that row alone (Algorithm 1, tie reading by position)."""
+    rp, ci, val, M = _pin_rows_problem()
+    nf = M.shape[1]
+    rows = np.array([8, 0, 3, 11, 5, 9, 2, 8, 10, 6], np.int64)
+    sel_ptr, sel = ora.core_select_rows(rows, rp, ci, M.astype(np.float64), num, den, min_keep)
+    off = 0
+    assert sel_ptr[0] == 0
+    for t, i in enumerate(rows):
+        n = int(rp[i + 1] - rp[i])
+        s = min(n, max(min_keep, (n * num) // den))
+        assert sel_ptr[t + 1] - sel_ptr[t] == nf * s
+        off += nf * s
+        X = M[ci[rp[i]:rp[i + 1]]].astype(np.float64)
+        mask = brute_mask(X, s) if n else np.zeros((0, nf), bool)
+        block = sel[sel_ptr[t]:sel_ptr[t + 1]].reshape(nf, s) if s else np.zeros((nf, 0), np.int32)
+        for a in range(nf):
+            assert block[a].tolist() == np.nonzero(mask[:, a])[0].tolist(), (i, a)
+    assert sel_ptr[-1] == off == len(sel)
+
+
+@pytest.mark.parametrize("num,den,min_keep", [(1, 10, 1), (1, 4, 0), (1, 1, 1)])
+def test_half_sweep_rows_pinned_by_dense_estimator(ora, num, den, min_keep):
+    """half_sweep_rows on a permuted row list: each output row equals the dense
+    brute-force estimator of its own row (X* built explicitly, LAPACK solve),
+    empty rows and s = 0 rows give zeros; and listing every row in order gives
+    the full half-sweep bit for bit."""
+    rp, ci, val, M = _pin_rows_problem(43)
+    M = (M + 0.01 * np.arange(M.size).reshape(M.shape) / M.size).astype(np.float32)  # fewer exact ties
+    lam = 0.07
+    rows = np.array([8, 3, 0, 11, 7, 5, 9, 1], np.int64)
+    out, st = ora.half_sweep_rows(rows, rp, ci, val, M.astype(np.float64), lam, num, den, min_keep)
+    for t, i in enumerate(rows):
+        b, e = int(rp[i]), int(rp[i + 1])
+        n = e - b
+        s = min(n, max(min_keep, (n * num) // den))
+        if n == 0 or s == 0:
+            assert np.all(out[t] == 0.0), i
+            continue
+        X = M[ci[b:e]].astype(np.float64)
+        ref = dense_core(X, val[b:e].astype(np.float64), lam, s)
+        np.testing.assert_allclose(out[t], ref, rtol=1e-8, atol=1e-11)
+    assert st[0] == 1  # row 0 is the listed empty row
+    full, fst = ora.half_sweep(rp, ci, val, M.astype(np.float64), lam, num, den, min_keep)
+    allr, ast = ora.half_sweep_rows(np.arange(len(rp) - 1), rp, ci, val, M.astype(np.float64), lam, num,
+                                    den, min_keep)
+    assert np.array_equal(full, allr) and np.array_equal(fst, ast)
+
+
+def test_singular_core_system_exact_fallback(ora):
+    """A row whose every column keeps the same dominant entry: X*^T X has rank 1
+    in exact arithmetic (factor values are powers of two, so every product,
+    sum and multiplier is exact), the pivoted LU meets a zero pivot and the row
+    takes the full-data update of eq. (U), here the least-squares solution
+    (lambda = 0, X of full column rank).  With s = n the system is eq. (U)
+    itself: a rank-deficient one gives u = 0 and is no fallback."""
+    rng = np.random.default_rng(5)
+    nf = 4
+    X = rng.choice([-1.0, -0.5, 0.5, 1.0], size=(12, nf))
+    X[3] = 2.0  # the dominant design row
+    y = rng.standard_normal(12)
+    u, st = ora.core_row(X, y, 0.0, 1)
+    assert st == 2
+    np.testing.assert_allclose(u, np.linalg.lstsq(X, y, rcond=None)[0], rtol=1e-10)
+    u, st = ora.core_row(X[:2], y[:2], 0.0, 2)  # n = s = 2 < n_f, lambda = 0: singular eq. (U)
+    assert st == 3 and np.all(u == 0.0)
+    # the half-sweep counts only the core fallback: row 0 rates all 12 design
+    # rows (s = 1), row 1 rates one (s = n = 1, a singular eq. (U) at lambda = 0)
+    rp, ci = _csr_from_rows([np.arange(12), np.array([4])])
+    vals = np.concatenate([y, y[4:5]]).astype(np.float32)
+    out, cnt = ora.half_sweep(rp, ci, vals, X, 0.0, 1, 12, 1)
+    assert cnt[1] == 1 and np.all(out[1] == 0.0)
+    np.testing.assert_allclose(out[0], np.linalg.lstsq(X, vals[:12].astype(np.float64), rcond=None)[0],
+                               rtol=1e-10)

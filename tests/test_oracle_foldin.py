@@ -87,3 +87,25 @@ def test_relative_residual_pins():
         np.testing.assert_allclose(A[a], X[k[a], a] * X[k[a]] + lam * n * np.eye(nf)[a], rtol=1e-14)
         assert abs(b[a] - X[k[a], a] * y[k[a]]) < 1e-14
     assert foldin.relative_residual(np.zeros((0, nf)), np.zeros(0), lam, 0, np.ones(nf)) == math.inf
+
+
+def test_forward_hand_worked_network():
+    """A 2 -> 2 -> 2 -> 2 network whose pre-activations are 0 or +-10, where
+    GELU is 0, 10 and about -7.6e-23: the output follows by hand.  A dropped
+    bias or a transposed weight matrix changes it.  Second network: the only
+    activation is GELU(1) = Phi(1), so out = 2 Phi(1) - 1 = P(|Z| < 1), the
+    tabulated 0.682689492137086."""
+    W1 = np.array([[3.0, 1.0], [-2.0, -4.0]])
+    c1 = np.array([5.0, 0.0])
+    W2 = np.array([[0.1, 5.0], [0.2, 0.0]])
+    c2 = np.array([-1.0, 8.0])
+    W3 = np.array([[1.0, 0.5], [2.0, -0.25]])
+    c3 = np.array([0.5, 1.0])
+    theta = foldin.pack({"W1": W1, "c1": c1, "W2": W2, "c2": c2, "W3": W3, "c3": c3}, 2, 2)
+    out, _ = foldin.forward(theta, np.array([[1.0, 2.0]]), 2, 2)
+    # z1 = [10, -10] -> h1 = [10, ~0]; z2 = [~0, 10] -> h2 = [~0, 10]; out = W3 h2 + c3
+    np.testing.assert_allclose(out[0], [5.5, -1.5], rtol=0, atol=1e-12)
+    theta1 = foldin.pack({"W1": [[1.0]], "c1": [0.0], "W2": [[0.0]], "c2": [1.0], "W3": [[2.0]], "c3": [-1.0]},
+                         1, 1)
+    out1, _ = foldin.forward(theta1, np.array([[0.3]]), 1, 1)
+    assert abs(out1[0, 0] - 0.682689492137086) <= 1e-15
