@@ -177,12 +177,13 @@ static int ora_gepp(int32_t n, double *A, double *b, double tol) {
 }
 
 /* Solve G x = b for symmetric positive definite G by Cholesky G = L L^T.
- * Returns 1 if a diagonal is not positive. */
-static int ora_cholesky_solve(int32_t n, double *G, double *b) {
+ * Returns 1 if a pivot d_j (the diagonal before its square root, the pivot an
+ * elimination without row exchanges meets) is <= tol. */
+static int ora_cholesky_solve(int32_t n, double *G, double *b, double tol) {
     for (int32_t j = 0; j < n; ++j) {
         double d = G[j * n + j];
         for (int32_t c = 0; c < j; ++c) d -= G[j * n + c] * G[j * n + c];
-        if (!(d > 0.0)) return 1;
+        if (!(d > tol)) return 1;
         d = sqrt(d);
         G[j * n + j] = d;
         for (int32_t i = j + 1; i < n; ++i) {
@@ -219,7 +220,10 @@ static int ora_full_row(int64_t n, int32_t nf, const double *X, const double *y,
         for (int64_t k = 0; k < n; ++k) acc += X[k * nf + a] * y[k];
         u[a] = acc;
     }
-    int bad = ora_cholesky_solve(nf, G, u);
+    /* the singularity rule of the core system: a pivot <= n_f 2^-52 max|G| */
+    double gmax = 0.0;
+    for (int64_t e = 0; e < (int64_t)nf * nf; ++e) gmax = fmax(gmax, fabs(G[e]));
+    int bad = ora_cholesky_solve(nf, G, u, (double)nf * ldexp(1.0, -52) * gmax);
     if (bad) for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
     free(G);
     return bad;
