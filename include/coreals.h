@@ -136,6 +136,25 @@ als_status half_sweep_users(als_ctx *c, const float *M, float *U, als_sweep_stat
  * U: [n_u * n_f] input; M: [n_m * n_f] output. */
 als_status half_sweep_items(als_ctx *c, const float *U, float *M, als_sweep_stats *st);
 
+/* Half-sweep of side 0 (users, other = M, out = U) or side 1 (items,
+ * other = U, out = M) exactly as half_sweep_users / half_sweep_items, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * serving loops, hosts that forbid it): the call's scratch (event counters,
+ * row-queue counters, heavy-row partial systems and refinement residuals)
+ * lives in a fixed array of the library in device memory,
+ * half_sweep_noalloc_scratch_bytes() bytes per GPU (about 18 MB), held from
+ * the first call on that GPU until the process ends, instead of in the
+ * context's workspace.  It calls no allocator.  The context must have been
+ * created with heavy_pair_cap <= half_sweep_noalloc_pair_cap() (1024);
+ * ALS_E_ARG otherwise.  Results are identical to the workspace entry points'.
+ * The array keeps the last call's contents and every call on a GPU shares
+ * it: calls that overlap in time on one GPU (several streams or threads)
+ * race.  Never captured into the context's graphs; no profiling marks.  st
+ * as for half_sweep_users. */
+als_status half_sweep_noalloc(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st);
+size_t half_sweep_noalloc_scratch_bytes(void);
+int64_t half_sweep_noalloc_pair_cap(void);
+
 /* Number of positions core_select writes for rows [row_begin, row_end) of one
  * side: sum over rows of n_f * s_i.  side 0 = users (rows of R), 1 = items
  * (columns of R).  *count is (host).  Syncs. */

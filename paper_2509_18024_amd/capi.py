@@ -77,7 +77,8 @@ EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_ite
            "als_class_counts", "als_use_graphs", "als_destroy", "als_last_error",
            "foldin_param_count", "foldin_workspace_size", "foldin_create", "foldin_get_params",
            "foldin_set_params", "foldin_forward", "foldin_grad", "foldin_adamw", "foldin_train",
-           "foldin_answer", "foldin_destroy", "foldin_last_error"]
+           "foldin_answer", "foldin_destroy", "foldin_last_error",
+           "half_sweep_noalloc", "half_sweep_noalloc_scratch_bytes", "half_sweep_noalloc_pair_cap"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
 NPROF = 12
@@ -103,6 +104,12 @@ def load():
         f = getattr(L, name)
         f.restype = i32
         f.argtypes = [vp, vp, vp, ctypes.POINTER(als_sweep_stats)]
+    L.half_sweep_noalloc.restype = i32
+    L.half_sweep_noalloc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(als_sweep_stats)]
+    L.half_sweep_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    L.half_sweep_noalloc_scratch_bytes.argtypes = []
+    L.half_sweep_noalloc_pair_cap.restype = i64
+    L.half_sweep_noalloc_pair_cap.argtypes = []
     L.core_select_count.restype = i32
     L.core_select_count.argtypes = [vp, i32, i64, i64, ctypes.POINTER(ctypes.c_int64)]
     L.core_select.restype = i32
@@ -174,6 +181,20 @@ def half_sweep_items(ctx, U_ptr: int, M_ptr: int, stats: bool = False):
     st = als_sweep_stats() if stats else None
     _check(load().half_sweep_items(ctx, U_ptr, M_ptr, ctypes.byref(st) if st else None), ctx)
     return st
+
+
+def half_sweep_noalloc(ctx, side: int, other_ptr: int, out_ptr: int, stats: bool = False):
+    st = als_sweep_stats() if stats else None
+    _check(load().half_sweep_noalloc(ctx, side, other_ptr, out_ptr, ctypes.byref(st) if st else None), ctx)
+    return st
+
+
+def half_sweep_noalloc_scratch_bytes() -> int:
+    return int(load().half_sweep_noalloc_scratch_bytes())
+
+
+def half_sweep_noalloc_pair_cap() -> int:
+    return int(load().half_sweep_noalloc_pair_cap())
 
 
 def core_select_count(ctx, side: int, row_begin: int, row_end: int) -> int:

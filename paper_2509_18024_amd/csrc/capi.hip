@@ -141,18 +141,25 @@ als_status fail(als_ctx *c, als_status st, const char *fmt, const char *detail =
         if (e_ != hipSuccess) return fail((ctx), ALS_E_DEVICE, "HIP error: %s", hipGetErrorString(e_)); \
     } while (0)
 
+SweepScratch workspace_scratch(const als_ctx *c) { return SweepScratch{c->stats, c->queues, c->partials, c->resid}; }
+
 // All launches of one half-sweep, in stream order (also what a graph captures).
 // chk (fold-in answers, users side): keep each row's candidate when its
 // relative residual passes, solve the others exactly.
-als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *out, const CheckArgs *chk) {
+// sc: where the call's counters, row queues, partial systems and residuals
+// live (the context's workspace, or the allocation-free entry point's array);
+// marks: record the profiling events when profiling is on.
+als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *out, const CheckArgs *chk,
+                              const SweepScratch &sc, bool marks = true) {
     const Side &S = c->side[side];
-    unsigned int *queues = c->queues + side * 16;
+    unsigned int *queues = sc.queues + side * 16;
+    const bool prof = marks && c->profiling;
     // counters are cleared by a kernel, not a memset node, so that replays of a
     // captured graph start from zero every time
-    HIP_CHECK(c, launch_zero_u64(c->stats, NSTATS, c->stream));
+    HIP_CHECK(c, launch_zero_u64(sc.stats, NSTATS, c->stream));
     HIP_CHECK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(queues), 8, c->stream));
     auto mark_begin = [&](int cls, als_ctx::Mark &mk) -> hipError_t {
-        if (!c->profiling) return hipSuccess;
+        if (!prof) return hipSuccess;
         hipError_t e = hipEventCreate(&mk.start);
         if (e == hipSuccess) e = hipEventCreate(&mk.stop);
         mk.side = side;
@@ -161,7 +168,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         return e;
     };
     auto mark_end = [&](als_ctx::Mark &mk) -> hipError_t {
-        if (!c->profiling) return hipSuccess;
+        if (!prof) return hipSuccess;
         hipError_t e = hipEventRecord(mk.stop, c->stream);
         c->marks.push_back(mk);
         return e;
@@ -180,7 +187,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         a.num = c->p.budget_num;
         a.den = c->p.budget_den;
         a.min_keep = c->p.min_keep;
-        a.stats = c->stats;
+        a.stats = sc.stats;
         a.queue = queues + cls;
         a.guess = chk ? chk->guess : nullptr;
         a.tol = chk ? chk->tol : 0.f;
@@ -217,12 +224,12 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.pair_off = H.pair_off;
         h.cutT = H.cutT;
         h.cutK = H.cutK;
-        h.partials = c->partials;
-        h.resid = c->resid;
+        h.partials = sc.partials;
+        h.resid = sc.resid;
         h.refine = 0;
         h.keep = c->bf16 ? 1 : 0;
         h.fp64res = c->fp64res ? 1 : 0;
-        h.stats = c->stats;
+        h.stats = sc.stats;
         h.queue = queues + CLS_HEAVY;
         h.guess = nullptr;
         h.tol = 0.f;
@@ -291,7 +298,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
             }
             hipGraph_t g = nullptr;
             HIP_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            als_status rs = enqueue_half_sweep(c, side, other, out, nullptr);
+            als_status rs = enqueue_half_sweep(c, side, other, out, nullptr, workspace_scratch(c));
             hipError_t ec = hipStreamEndCapture(c->stream, &g);
             if (rs != ALS_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -306,18 +313,10 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
         }
         HIP_CHECK(c, hipGraphLaunch(G.exec, c->stream));
     } else {
-        als_status rs = enqueue_half_sweep(c, side, other, out, nullptr);
+        als_status rs = enqueue_half_sweep(c, side, other, out, nullptr, workspace_scratch(c));
         if (rs != ALS_OK) return rs;
     }
-    if (st) {
-        unsigned long long h[NSTATS];
-        HIP_CHECK(c, hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-        HIP_CHECK(c, hipStreamSynchronize(c->stream));
-        st->n_empty = (int64_t)h[ST_EMPTY];
-        st->n_singular_fallback = (int64_t)h[ST_FALLBACK];
-        st->n_fp64_residual = (int64_t)h[ST_FP64RES];
-        st->n_rows = c->side[side].n_rows;
-    }
+    if (st) return fill_stats(c, side, c->stats, st);
     return ALS_OK;
 }
 
@@ -328,7 +327,7 @@ namespace coreals {
 als_status enqueue_checked_users(als_ctx *c, const float *M, float *out, const CheckArgs &chk) {
     if (!c) return ALS_E_STATE;
     HIP_CHECK(c, launch_zero_u64(c->stats, NSTATS, c->stream));
-    return enqueue_half_sweep(c, 0, M, out, &chk);
+    return enqueue_half_sweep(c, 0, M, out, &chk, workspace_scratch(c));
 }
 
 als_status read_stats(als_ctx *c, unsigned long long *h) {
@@ -338,6 +337,25 @@ als_status read_stats(als_ctx *c, unsigned long long *h) {
 }
 
 als_status set_error(als_ctx *c, als_status st, const char *msg) { return fail(c, st, "%s", msg); }
+
+als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als_sweep_stats *st) {
+    unsigned long long h[NSTATS];
+    HIP_CHECK(c, hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(c, hipStreamSynchronize(c->stream));
+    st->n_empty = (int64_t)h[ST_EMPTY];
+    st->n_singular_fallback = (int64_t)h[ST_FALLBACK];
+    st->n_fp64_residual = (int64_t)h[ST_FP64RES];
+    st->n_rows = c->side[side].n_rows;
+    return ALS_OK;
+}
+
+als_status enqueue_half_sweep_scratch(als_ctx *c, int side, const float *other, float *out, const SweepScratch &sc) {
+    if (!c) return ALS_E_STATE;
+    if (side == 1 && c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
+    if (!other || !out) return fail(c, ALS_E_ARG, "NULL factor pointer%s");
+    if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
+    return enqueue_half_sweep(c, side, other, out, nullptr, sc, false);
+}
 
 }  // namespace coreals
 

@@ -275,6 +275,23 @@ struct als_ctx {
 
 namespace coreals {
 
+// Per-call scratch of a half-sweep: event counters, row-queue counters,
+// heavy-row partial systems and residuals.  Batches of the heavy-row plan
+// hold at most the context's pair_cap pairs, which the partial and residual
+// arrays must fit.
+struct SweepScratch {
+    unsigned long long *stats;  // [NSTATS]
+    unsigned int *queues;       // [2 * 16]
+    float *partials;            // [pair_cap * (NF + 1) * 64]
+    double *resid;              // [pair_cap * 128]
+};
+
+// Enqueue one half-sweep of c with the given scratch (no graph, no profiling
+// marks); argument errors as for half_sweep_users / half_sweep_items.
+als_status enqueue_half_sweep_scratch(als_ctx *c, int side, const float *other, float *out, const SweepScratch &sc);
+// Copy per-row event counters to st (syncs the context's stream).
+als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als_sweep_stats *st);
+
 // Users half-sweep of c in fold-in check mode (stats cleared first); used by
 // the fold-in entry points.
 als_status enqueue_checked_users(als_ctx *c, const float *M, float *out, const CheckArgs &chk);
