@@ -74,7 +74,9 @@ typedef enum {
 
 typedef struct {
     int64_t n_u, n_m, nnz;
-    int32_t n_f;                 /* 1 <= n_f <= 64                            */
+    int32_t n_f;                 /* 1 <= n_f <= 128; ranks above 64 solve every
+                                    row with a workgroup (heavy-row schedule),
+                                    and foldin_answer needs n_f <= 64           */
     const int64_t *row_ptr;      /* CSR of R (users x items), device          */
     const int32_t *col_idx;
     const float *val;
@@ -91,7 +93,7 @@ typedef struct {
                                     are split across workgroups; 0 = default 1024 */
     int32_t heavy_chunk;         /* entries per partial Gram of such rows; 0 = 1024 */
     int32_t heavy_pair_cap;      /* partial systems kept in scratch at once (sizes the
-                                    workspace); 0 = 65536 */
+                                    workspace); 0 = 65536 (8192 for n_f > 64) */
     int32_t light_blocks;        /* grid of the persistent light-row kernels, whose
                                     wavefronts take rows from an atomic counter;
                                     0 = one row per wavefront */

@@ -47,7 +47,7 @@ struct Layout {
     double *resid;
     uint16_t *key16;
     struct SideArrays {
-        int32_t *pair_slot, *pair_chunk, *cutT, *cutK;
+        int32_t *pair_slot, *pair_chunk, *cutT, *cutK, *flag;
         int64_t *pair_off;
     } side[2];
     void *temp;
@@ -55,14 +55,25 @@ struct Layout {
     size_t total;
 };
 
+// Ranks above 64 take the wide-rank kernels for every non-empty row.
+bool wide_of(const als_problem &p) { return p.n_f > NF; }
+
+// Light-row degree limit; 0 at wide ranks (every non-empty row is heavy).
 int32_t heavy_n_of(const als_problem &p) {
+    if (wide_of(p)) return 0;
     int32_t h = p.heavy_min_degree > 0 ? p.heavy_min_degree : DEFAULT_HEAVY_N;
     return h < 64 ? 64 : h;
 }
 
 int64_t pair_cap_of(const als_problem &p) {
-    return p.heavy_pair_cap > 0 ? std::min<int64_t>(p.heavy_pair_cap, PAIR_CAP) : PAIR_CAP;
+    const int64_t cap = wide_of(p) ? PAIR_CAP_WIDE : PAIR_CAP;
+    return p.heavy_pair_cap > 0 ? std::min<int64_t>(p.heavy_pair_cap, cap) : cap;
 }
+
+// Floats of one partial system (n x n plus the right-hand side), and cut
+// entries per heavy row.
+int64_t slot_floats(const als_problem &p) { return wide_of(p) ? (int64_t)(NFW + 1) * NFW : (int64_t)(NF + 1) * 64; }
+int64_t cut_stride(const als_problem &p) { return wide_of(p) ? NFW : 64; }
 
 int32_t chunk_of(const als_problem &p) {
     int32_t c = p.heavy_chunk > 0 ? p.heavy_chunk : DEFAULT_CHUNK;
@@ -70,9 +81,10 @@ int32_t chunk_of(const als_problem &p) {
 }
 
 // Heavy rows have s > 32 or degree > heavy_n >= 64, so there are at most
-// nnz / 33 of them; their chunk pairs number at most nnz / chunk + n_heavy.
+// nnz / 33 of them (at wide ranks every non-empty row); their chunk pairs
+// number at most nnz / chunk + n_heavy.
 int64_t heavy_bound(const als_problem &p, int64_t n_rows) {
-    return std::min<int64_t>(n_rows, p.nnz / 33 + 1);
+    return std::min<int64_t>(n_rows, wide_of(p) ? p.nnz : p.nnz / 33 + 1);
 }
 
 int64_t pair_bound(const als_problem &p, int64_t n_rows) {
@@ -96,7 +108,7 @@ Layout carve(const als_problem &p, void *base) {
     L.err_flags = c.take<int>(4);
     L.obj_partials = c.take<double>((size_t)5 * objective_blocks());
     L.obj_out = c.take<double>(4);
-    L.partials = c.take<float>((size_t)pair_cap_of(p) * (NF + 1) * 64);
+    L.partials = c.take<float>((size_t)pair_cap_of(p) * slot_floats(p));
     L.resid = c.take<double>((size_t)pair_cap_of(p) * 128);
     // core-elements runs: top 16 bits of each |x| of the fixed factor
     // matrix, read by the first two selection passes
@@ -108,8 +120,9 @@ Layout carve(const als_problem &p, void *base) {
         L.side[sd].pair_slot = c.take<int32_t>((size_t)pb);
         L.side[sd].pair_chunk = c.take<int32_t>((size_t)pb);
         L.side[sd].pair_off = c.take<int64_t>((size_t)hb + 1);
-        L.side[sd].cutT = c.take<int32_t>((size_t)hb * 64);
-        L.side[sd].cutK = c.take<int32_t>((size_t)hb * 64);
+        L.side[sd].cutT = c.take<int32_t>((size_t)hb * cut_stride(p));
+        L.side[sd].cutK = c.take<int32_t>((size_t)hb * cut_stride(p));
+        L.side[sd].flag = c.take<int32_t>(wide_of(p) ? (size_t)hb : 0);
     }
     size_t tb = uo ? 0 : csc_temp_bytes(p.nnz, p.n_m);
     size_t tp = perm_temp_bytes(uo ? p.n_u : std::max(p.n_u, p.n_m));
@@ -123,7 +136,7 @@ bool sizes_ok(const als_problem *p) {
     if (!p) return false;
     if (p->n_u < 0 || p->n_m < 0 || p->nnz < 0) return false;
     if (p->n_u > INT32_MAX || p->n_m > INT32_MAX || p->nnz > INT32_MAX) return false;
-    if (p->n_f < 1 || p->n_f > NF) return false;
+    if (p->n_f < 1 || p->n_f > NFW) return false;
     return true;
 }
 
@@ -196,7 +209,8 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         if (a.count <= 0) continue;
         als_ctx::Mark mk{};
         HIP_CHECK(c, mark_begin(cls, mk));
-        if (chk) HIP_CHECK(c, launch_check_class(cls, a, c->light_blocks, c->stream));
+        if (c->wide) HIP_CHECK(c, launch_wide_empty(a, c->stream));  // the only light rows: no entries
+        else if (chk) HIP_CHECK(c, launch_check_class(cls, a, c->light_blocks, c->stream));
         else HIP_CHECK(c, launch_sweep_class(cls, a, c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(mk));
     }
@@ -224,11 +238,15 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.pair_off = H.pair_off;
         h.cutT = H.cutT;
         h.cutK = H.cutK;
+        h.cstride = c->wide ? NFW : 64;
+        h.col_base = 0;
+        h.flag = c->flag[side];
+        h.fallback = 0;
         h.partials = sc.partials;
         h.resid = sc.resid;
         h.refine = 0;
         h.keep = c->bf16 ? 1 : 0;
-        h.fp64res = c->fp64res ? 1 : 0;
+        h.fp64res = c->fp64res;
         h.stats = sc.stats;
         h.queue = queues + CLS_HEAVY;
         h.guess = nullptr;
@@ -244,10 +262,47 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
             als_ctx::Mark mk{};
             HIP_CHECK(c, mark_begin(PROF_HSELECT, mk));
             HIP_CHECK(c, launch_heavy_select(h, 0, c->stream));
+            if (c->wide) {
+                // columns 64 .. n_f - 1: a second launch with its own row counter
+                h.col_base = 64;
+                h.queue = queues + 8;
+                HIP_CHECK(c, launch_heavy_select(h, 0, c->stream));
+                h.col_base = 0;
+                h.queue = queues + CLS_HEAVY;
+            }
             h.key16 = nullptr;
             HIP_CHECK(c, mark_end(mk));
         }
         for (const auto &b : H.batches) {
+            if (c->wide) {
+                if (chk) return fail(c, ALS_E_STATE, "fold-in answers need n_f <= 64%s");
+                als_ctx::Mark mg{}, ms{};
+                HIP_CHECK(c, mark_begin(PROF_HGRAM, mg));
+                HIP_CHECK(c, launch_wide_gram(h, b.pair_begin, b.pair_end, !c->bf16, c->stream));
+                HIP_CHECK(c, mark_end(mg));
+                HIP_CHECK(c, mark_begin(PROF_HSOLVE, ms));
+                h.refine = 0;
+                HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                // rows whose core system was singular: full-data Gram (FP32
+                // products) and solve, eq. (U)
+                h.fallback = 1;
+                HIP_CHECK(c, launch_wide_gram(h, b.pair_begin, b.pair_end, true, c->stream));
+                HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                h.fallback = 0;
+                HIP_CHECK(c, mark_end(ms));
+                if (c->bf16) {
+                    als_ctx::Mark mr{}, m2{};
+                    HIP_CHECK(c, mark_begin(PROF_HRESID, mr));
+                    HIP_CHECK(c, launch_wide_resid(h, b.pair_begin, b.pair_end, c->stream));
+                    HIP_CHECK(c, mark_end(mr));
+                    HIP_CHECK(c, mark_begin(PROF_HREFINE, m2));
+                    h.refine = 1;
+                    HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                    h.refine = 0;
+                    HIP_CHECK(c, mark_end(m2));
+                }
+                continue;
+            }
             if (chk) {
                 // candidate residuals of the batch's rows; accepted rows are then
                 // skipped by every kernel below (path 0)
@@ -369,7 +424,7 @@ size_t als_workspace_size(const als_problem *p) {
 als_status als_init(const als_problem *p, als_ctx **out) {
     if (!out) return fail(nullptr, ALS_E_ARG, "out is NULL%s");
     *out = nullptr;
-    if (!sizes_ok(p)) return fail(nullptr, ALS_E_ARG, "invalid sizes (need 1 <= n_f <= 64, sizes < 2^31)%s");
+    if (!sizes_ok(p)) return fail(nullptr, ALS_E_ARG, "invalid sizes (need 1 <= n_f <= 128, sizes < 2^31)%s");
     if (!(p->lambda >= 0.0)) return fail(nullptr, ALS_E_ARG, "lambda must be >= 0%s");
     if (p->budget_den == 0 || p->budget_num == 0 || p->budget_num > p->budget_den)
         return fail(nullptr, ALS_E_ARG, "budget rate must satisfy 0 < num <= den%s");
@@ -399,7 +454,12 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->resid = L.resid;
     c->key16 = p->budget_num < p->budget_den ? L.key16 : nullptr;
     c->bf16 = p->precision != ALS_PREC_FP32;
-    c->fp64res = p->precision == ALS_PREC_BF16_IR_FP64RES || (p->precision == ALS_PREC_AUTO && p->lambda < 1e-3);
+    // FP64 residual: always (FP64RES), per row (AUTO: lambda < 1e-3 and a
+    // large pivot ratio), or never
+    c->fp64res = p->precision == ALS_PREC_BF16_IR_FP64RES ? RES_FP64
+                 : p->precision == ALS_PREC_AUTO          ? RES_PER_ROW
+                                                          : RES_FP32;
+    c->wide = wide_of(*p);
     c->heavy_n = heavy_n_of(*p);
     c->chunk = chunk_of(*p);
     c->pair_cap = pair_cap_of(*p);
@@ -479,6 +539,7 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         H.pair_off = L.side[sd].pair_off;
         H.cutT = L.side[sd].cutT;
         H.cutK = L.side[sd].cutK;
+        c->flag[sd] = L.side[sd].flag;
         if (H.n_heavy == 0) continue;
         if (H.n_heavy > heavy_bound(*p, S.n_rows)) return bail(ALS_E_STATE, "heavy-row bound violated");
         std::vector<int32_t> rows((size_t)H.n_heavy);
@@ -564,11 +625,12 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
     if (total > sel_cap) return fail(c, ALS_E_NOMEM, "sel_pos capacity below core_select_count%s");
     // heavy rows of the range: cuts by the sweep's own heavy-row selection,
     // stored in the partial scratch, processed in sub-ranges that fit it
-    const int64_t sub = c->pair_cap * (NF + 1) * 64 / 128;
+    const int64_t cs = cut_stride(c->p);
+    const int64_t sub = c->pair_cap * slot_floats(c->p) / (2 * cs);
     for (int64_t r0 = row_begin; r0 < row_end; r0 += sub) {
         const int64_t r1 = std::min(row_end, r0 + sub);
         int32_t *cutT = reinterpret_cast<int32_t *>(c->partials);
-        int32_t *cutK = cutT + (r1 - r0) * 64;
+        int32_t *cutK = cutT + (r1 - r0) * cs;
         HeavyArgs h{};
         h.ptr = S.ptr;
         h.idx = S.idx;
@@ -583,7 +645,13 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
         h.heavy_n = c->heavy_n;
         h.cutT = cutT;
         h.cutK = cutK;
+        h.cstride = (int32_t)cs;
+        h.col_base = 0;
         HIP_CHECK(c, launch_heavy_select(h, r0, c->stream));
+        if (c->wide) {
+            h.col_base = 64;
+            HIP_CHECK(c, launch_heavy_select(h, r0, c->stream));
+        }
         SelectArgs a;
         a.ptr = S.ptr;
         a.idx = S.idx;
@@ -599,7 +667,8 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
         a.sel_pos = sel_pos;
         a.cutT = cutT;
         a.cutK = cutK;
-        HIP_CHECK(c, launch_select(a, c->stream));
+        if (c->wide) HIP_CHECK(c, launch_select_wide(a, c->stream));
+        else HIP_CHECK(c, launch_select(a, c->stream));
     }
     return ALS_OK;
 }

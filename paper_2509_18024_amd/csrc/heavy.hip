@@ -72,8 +72,10 @@ struct HeavySelLds {
     int flag;
 };
 
+// Rows the heavy-row selection cuts: heavy, with something to drop and
+// something to keep (s = 0 keeps nothing and needs no cut).
 __device__ __forceinline__ bool is_heavy_core(int n, int s, int heavy_n) {
-    return class_of(n, s, heavy_n) == CLS_HEAVY && s < n;
+    return class_of(n, s, heavy_n) == CLS_HEAVY && s < n && s > 0;
 }
 
 // Factor-row gathers of the selection passes: lane a reads entry a of one
@@ -244,8 +246,11 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const int w = wave_index();
     const int lane = tid & 63;
     const int nf = a.nf;
-    const RowGather<BUF> R(a.other, nf, lane);
-    const KeyGather16 R16(a.key16, nf, lane);
+    // lane a ranks column col_base + a (ranks above 64: two launches, one per
+    // half of the columns)
+    const int col = a.col_base + lane;
+    const RowGather<BUF> R(a.other, nf, col);
+    const KeyGather16 R16(a.key16, nf, col);
     __shared__ int64_t next_t;
     int64_t t = blockIdx.x;
     for (;;) {
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         if (tid < 64) {
             // padded columns (a >= n_f, all-zero keys) get the cut of a column
             // of equal keys: the first s positions
-            const bool pad = tid >= nf;
+            const bool pad = a.col_base + tid >= nf;
             S.prefix[tid] = 0;
             S.rem[tid] = s;
             S.done[tid] = pad ? 1 : 0;
@@ -458,8 +463,8 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         }
         __syncthreads();
         if (tid < 64) {
-            a.cutT[t * 64 + tid] = S.T[tid];
-            a.cutK[t * 64 + tid] = S.K[tid];
+            a.cutT[t * a.cstride + a.col_base + tid] = S.T[tid];
+            a.cutK[t * a.cstride + a.col_base + tid] = S.K[tid];
         }
         __syncthreads();
         if (!a.queue) t += gridDim.x;
@@ -503,13 +508,18 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
             // a refinement step follows: keep the factors for it
             int my_step;
             float r[1] = {rhs};
-            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step);
+            float pmin, pmax;
+            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step, pmin, pmax);
+            int need64 = 0;  // bit 16 of the kept step: FP64 residual for this row
             if (ok) {
                 u = lu_back(A, r, lane, my_step, L);
 #pragma unroll
                 for (int b = 0; b < NF; ++b) fac[b * 64 + lane] = A[b];
+                if (a.fp64res == RES_FP64) need64 = 1;
+                else if (a.fp64res == RES_PER_ROW)
+                    need64 = ((double)a.lam < FP64_LAMBDA && pmax > FP64_PIVOT_RATIO * pmin) ? 1 : 0;
             }
-            fac[NF * 64 + lane] = __int_as_float(ok ? my_step : -1);
+            fac[NF * 64 + lane] = __int_as_float(ok ? (my_step | (need64 << 16)) : -1);
         } else {
             ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         }
@@ -545,8 +555,10 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_refine(HeavyArgs a, int64_t 
         if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
         const int n = (int)(a.ptr[i + 1] - a.ptr[i]);
         const float *fac = a.partials + (a.pair_off[slot] - pair_base) * (int64_t)(NF + 1) * 64;
-        const int my_step = __float_as_int(fac[NF * 64 + lane]);
-        if (my_step < 0) continue;  // the first solve used the full-data fallback
+        const int kept_step = __float_as_int(fac[NF * 64 + lane]);
+        if (kept_step < 0) continue;  // the first solve used the full-data fallback
+        const int my_step = kept_step & 0xFFFF;
+        const bool need64 = (kept_step >> 16) & 1;
         float A[NF];
 #pragma unroll
         for (int b = 0; b < NF; ++b) A[b] = fac[b * 64 + lane];
@@ -559,7 +571,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_refine(HeavyArgs a, int64_t 
         float r[1] = {(float)rho};
         fwd_all_u<1>(std::make_integer_sequence<int, NF>{}, A, r, my_step);
         const float d = lu_back(A, r, lane, my_step, L);
-        if (a.fp64res && lane == 0) atomicAdd(&a.stats[ST_FP64RES], 1ull);
+        if (need64 && lane == 0) atomicAdd(&a.stats[ST_FP64RES], 1ull);
         if (lane < a.nf) a.out[i * a.nf + lane] = u0 + d;
     }
 }
@@ -869,9 +881,42 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
 // k of x_ka (y_k - x_k . u), with u the row's current solution (in `out`).
 // Lane k forms y_k - x_k . u for the staged rows, lane a then accumulates its
 // column.  FP64 accumulates in double throughout.
-template <bool FP64>
+// The accumulation type is chosen per row: FP64 when the row's first solve
+// asked for it (bit 16 of its kept pivot step), FP32 otherwise.
+template <typename acc_t>
+__device__ __forceinline__ void heavy_resid_pair(const HeavyArgs &a, WaveLds &L, RowCtx &r, const Cut &c, int chunk,
+                                                 int n, int64_t p, int64_t pair_begin, int lane) {
+    acc_t acc = 0;
+    const int kb = chunk * a.chunk;
+    const int ke = min(n, kb + a.chunk);
+    for (int k0 = kb; k0 < ke; k0 += CK) {
+        stage(L, r, k0, lane);
+        const int mrows = min(CK, ke - k0);
+        acc_t rk = 0;
+        if (lane < mrows) {
+            acc_t dot = 0;
+#pragma unroll
+            for (int b4 = 0; b4 < NF / 4; ++b4) {
+                const float4 xr = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
+                dot += (acc_t)xr.x * (acc_t)L.urhs[4 * b4 + 0];
+                dot += (acc_t)xr.y * (acc_t)L.urhs[4 * b4 + 1];
+                dot += (acc_t)xr.z * (acc_t)L.urhs[4 * b4 + 2];
+                dot += (acc_t)xr.w * (acc_t)L.urhs[4 * b4 + 3];
+            }
+            rk = (acc_t)L.y[lane] - dot;
+        }
+        L.rres[lane] = (double)rk;
+        wave_sync();
+        for (int kk = 0; kk < mrows; ++kk) {
+            const float x = L.X[kk][lane];
+            if (kept(c, key_of(x), k0 + kk)) acc += (acc_t)x * (acc_t)L.rres[kk];
+        }
+        wave_sync();
+    }
+    a.resid[(p - pair_begin) * 64 + lane] = (double)acc;
+}
+
 __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
-    using acc_t = typename std::conditional<FP64, double, float>::type;
     __shared__ WaveLds lds[WPB];
     const int w = wave_index();
     const int lane = threadIdx.x & 63;
@@ -882,6 +927,10 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t p
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
         if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
+        // the row's kept pivot step (first pair's slot): -1 = no refinement
+        const float *fac = a.partials + (a.pair_off[slot] - pair_begin) * (int64_t)(NF + 1) * 64;
+        const int kept_step = __builtin_amdgcn_readfirstlane(__float_as_int(fac[NF * 64]));
+        if (kept_step < 0) continue;
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -892,34 +941,8 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t p
         else c = Cut{a.cutT[slot * 64 + lane], a.cutK[slot * 64 + lane], false, false};
         wave_sync();
         L.urhs[lane] = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
-        acc_t acc = 0;
-        const int kb = chunk * a.chunk;
-        const int ke = min(n, kb + a.chunk);
-        for (int k0 = kb; k0 < ke; k0 += CK) {
-            stage(L, r, k0, lane);
-            const int mrows = min(CK, ke - k0);
-            acc_t rk = 0;
-            if (lane < mrows) {
-                acc_t dot = 0;
-#pragma unroll
-                for (int b4 = 0; b4 < NF / 4; ++b4) {
-                    const float4 xr = *reinterpret_cast<const float4 *>(&L.X[lane][4 * b4]);
-                    dot += (acc_t)xr.x * (acc_t)L.urhs[4 * b4 + 0];
-                    dot += (acc_t)xr.y * (acc_t)L.urhs[4 * b4 + 1];
-                    dot += (acc_t)xr.z * (acc_t)L.urhs[4 * b4 + 2];
-                    dot += (acc_t)xr.w * (acc_t)L.urhs[4 * b4 + 3];
-                }
-                rk = (acc_t)L.y[lane] - dot;
-            }
-            L.rres[lane] = (double)rk;
-            wave_sync();
-            for (int kk = 0; kk < mrows; ++kk) {
-                const float x = L.X[kk][lane];
-                if (kept(c, key_of(x), k0 + kk)) acc += (acc_t)x * (acc_t)L.rres[kk];
-            }
-            wave_sync();
-        }
-        a.resid[(p - pair_begin) * 64 + lane] = (double)acc;
+        if ((kept_step >> 16) & 1) heavy_resid_pair<double>(a, L, r, c, chunk, n, p, pair_begin, lane);
+        else heavy_resid_pair<float>(a, L, r, c, chunk, n, p, pair_begin, lane);
     }
 }
 
@@ -1004,12 +1027,8 @@ hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_
 
 hipError_t launch_heavy_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
     if (pair_end <= pair_begin) return hipSuccess;
-    if (a.fp64res)
-        hipLaunchKernelGGL(k_heavy_resid<true>, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0,
-                           s, a, pair_begin, pair_end);
-    else
-        hipLaunchKernelGGL(k_heavy_resid<false>, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64),
-                           0, s, a, pair_begin, pair_end);
+    hipLaunchKernelGGL(k_heavy_resid, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s, a,
+                       pair_begin, pair_end);
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ namespace coreals {
 // Compile-time rank of the register-resident regression (lane a owns row a of
 // the n_f x n_f system).  Problems with n_f < 64 are padded with identity rows.
 constexpr int NF = 64;
+// Widest rank: ranks 64 < n_f <= NFW take the wide-rank kernels (wide.hip),
+// one workgroup per row with the n_f x n_f system spread over its threads.
+constexpr int NFW = 128;
 // Waves per workgroup of the row kernels; each wave solves its own rows.
 constexpr int WPB = 4;
 // Rows of the design matrix staged in LDS per chunk.
@@ -27,6 +30,14 @@ constexpr int HEAVY_CAP = 62;
 constexpr int DEFAULT_HEAVY_N = 1024;    // light rows have degree <= this
 constexpr int DEFAULT_CHUNK = 1024;      // entries per partial Gram of a heavy row
 constexpr int64_t PAIR_CAP = 65536;      // partial systems held in scratch at once
+constexpr int64_t PAIR_CAP_WIDE = 8192;  // the same at ranks above 64 (66 KB per system)
+// Refinement residual in FP64 when the precision mode asks for it per row:
+// lambda below this and a pivot ratio max|p| / min|p| of the row's LU above
+// FP64_PIVOT_RATIO (an estimate of the system's condition number).
+constexpr double FP64_LAMBDA = 1e-3;
+constexpr float FP64_PIVOT_RATIO = 1e3f;
+// fp64res modes of HeavyArgs
+enum Fp64Mode : int { RES_FP32 = 0, RES_FP64 = 1, RES_PER_ROW = 2 };
 
 // Degree classes that schedule a half-sweep.  Light rows (degree <= heavy_n
 // and budget s <= 32) are solved by one wavefront each: FULL when s == n
@@ -149,13 +160,17 @@ struct HeavyArgs {
     const int32_t *pair_slot;
     const int32_t *pair_chunk;
     const int64_t *pair_off;
-    int32_t *cutT;
+    int32_t *cutT;            // [heavy slot * cstride + column]
     int32_t *cutK;
+    int32_t cstride;          // cut entries per row: 64, or NFW at ranks above 64
+    int32_t col_base;         // selection: the launch ranks columns col_base .. + 63
     float *partials;
     double *resid;            // [pair_cap * 128] refinement / check residual partials
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
     int32_t keep;             // first solve keeps its LU factors for the refinement step
-    int32_t fp64res;          // residual accumulated in FP64
+    int32_t fp64res;          // Fp64Mode of the refinement residual
+    int32_t *flag;            // wide ranks: per heavy slot, 1 = core system singular
+    int32_t fallback;         // wide ranks: pass over the flagged rows with the full data
     unsigned long long *stats;
     unsigned int *queue;      // heavy-row selection counter (nullptr: grid-stride)
     // fold-in check mode (see SweepArgs); with path set, the Gram, solve and
@@ -206,6 +221,15 @@ hipError_t launch_heavy_check(const HeavyArgs &a, int64_t pair_begin, int64_t pa
 hipError_t launch_heavy_check_reduce(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
                                      hipStream_t s);
 
+// launchers (wide.hip): ranks 64 < n_f <= NFW.  Every non-empty row is a
+// heavy row (cuts from launch_heavy_select, one launch per 64 columns).
+hipError_t launch_wide_empty(const SweepArgs &a, hipStream_t s);
+hipError_t launch_wide_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, bool x6, hipStream_t s);
+hipError_t launch_wide_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slot_end, int64_t pair_base,
+                             hipStream_t s);
+hipError_t launch_wide_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
+hipError_t launch_select_wide(const SelectArgs &a, hipStream_t s);
+
 // launchers (setup.hip)
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
@@ -250,7 +274,9 @@ struct als_ctx {
     int64_t pair_cap = coreals::PAIR_CAP;
     int32_t light_blocks = 0;  // grid of the persistent light-row kernels (0: one row per wave)
     bool bf16 = false;     // heavy-row Gram on bf16 MFMA + one refinement step
-    bool fp64res = false;  // refinement residual in FP64
+    int fp64res = 0;       // Fp64Mode of the refinement residual
+    bool wide = false;     // 64 < n_f <= NFW: wide-rank kernels for every row
+    int32_t *flag[2] = {nullptr, nullptr};  // wide ranks: singular-system flags per heavy slot
     void *temp = nullptr;
     size_t temp_bytes = 0;
     std::string err;

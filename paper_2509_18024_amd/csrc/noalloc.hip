@@ -70,10 +70,13 @@ int64_t half_sweep_noalloc_pair_cap(void) { return NA_PAIR_CAP; }
 als_status half_sweep_noalloc(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st) {
     if (!c) return ALS_E_STATE;
     if (side != 0 && side != 1) return set_error(c, ALS_E_ARG, "side must be 0 or 1");
-    if (c->pair_cap > NA_PAIR_CAP)
+    // partial systems of 65 x 64 floats (ranks up to 64) or 129 x 128 (above)
+    const int64_t slot = c->wide ? (int64_t)(NFW + 1) * NFW : (int64_t)(NF + 1) * 64;
+    if (c->pair_cap * slot > NA_PAIR_CAP * (NF + 1) * 64)
         return set_error(c, ALS_E_ARG,
-                         "half_sweep_noalloc: the context's heavy_pair_cap exceeds the 1024 partial systems of "
-                         "the library's scratch array; create the context with heavy_pair_cap <= 1024");
+                         "half_sweep_noalloc: the context's heavy_pair_cap exceeds the partial systems of the "
+                         "library's scratch array; create the context with heavy_pair_cap <= 1024 (n_f <= 64) "
+                         "or <= 258 (n_f > 64)");
     unsigned char *base = nullptr;
     const hipError_t e = scratch_ptr(&base);
     if (e != hipSuccess) return set_error(c, ALS_E_DEVICE, hipGetErrorString(e));

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(OBJ_THREADS) void k_obj_rows(int64_t n_u, int32_t n
     for (int64_t i = wave; i < n_u; i += nwaves) {
         const int64_t b = row_ptr[i], e = row_ptr[i + 1];
         const float *u = U + i * nf;
-        if (lane < nf) pen += (double)(e - b) * (double)u[lane] * (double)u[lane];
+        for (int c = lane; c < nf; c += 64) pen += (double)(e - b) * (double)u[c] * (double)u[c];
         for (int64_t t = b + lane; t < e; t += 64) {
             const float *m = M + (int64_t)col_idx[t] * nf;
             float pred = 0.f;

@@ -346,7 +346,7 @@ def c4_precision(scale: float = 1.0, seed: int = 401, m0_seed: int = 402,
     with singular values log-spaced 1..1e3, no noise."""
     n_u = max(16, int(round(200_000 * scale)))
     n_m = max(16, int(round(50_000 * scale)))
-    n_f = 128 if scale >= 0.01 else 16
+    n_f = 128
     nnz = int(round(2e7 * scale))
     rng = np.random.default_rng(seed)
     keys = np.unique(rng.integers(0, n_u * n_m, size=int(nnz * 1.02) + 16, dtype=np.int64))
