@@ -58,8 +58,13 @@ typedef enum {
                                      FP32 LU, one refinement step with an FP32
                                      residual; light rows: FP32 Gram          */
     ALS_PREC_BF16_IR_FP64RES = 2, /* as above, refinement residual in FP64    */
-    ALS_PREC_AUTO = 3             /* BF16 + refinement, FP64 residual when
-                                     lambda < 1e-3, FP32 residual otherwise   */
+    ALS_PREC_AUTO = 3             /* BF16 + refinement with a per-row choice
+                                     from the condition estimate kappa =
+                                     |A|_inf |A^-1 e|_inf / |e|_inf (one extra
+                                     solve with the LU factors): kappa > 2^8,
+                                     the row's Gram is built again with FP32
+                                     products; lambda < 1e-3 and kappa > 2^10,
+                                     its refinement residual is FP64        */
 } als_precision;
 
 #define ALS_VALIDATE 1u   /* check ratings for NaN/Inf in als_init */
@@ -105,6 +110,8 @@ typedef struct {
                                     replaced by the full-data update eq. (U)      */
     int64_t n_fp64_residual;     /* rows refined with an FP64 residual            */
     int64_t n_rows;              /* rows solved in this half-sweep                */
+    int64_t n_fp32_gram;         /* ALS_PREC_AUTO: rows whose Gram was built again
+                                    with FP32 products (condition estimate)       */
 } als_sweep_stats;
 
 typedef struct {

@@ -122,7 +122,7 @@ Layout carve(const als_problem &p, void *base) {
         L.side[sd].pair_off = c.take<int64_t>((size_t)hb + 1);
         L.side[sd].cutT = c.take<int32_t>((size_t)hb * cut_stride(p));
         L.side[sd].cutK = c.take<int32_t>((size_t)hb * cut_stride(p));
-        L.side[sd].flag = c.take<int32_t>(wide_of(p) ? (size_t)hb : 0);
+        L.side[sd].flag = c.take<int32_t>((size_t)hb);
     }
     size_t tb = uo ? 0 : csc_temp_bytes(p.nnz, p.n_m);
     size_t tp = perm_temp_bytes(uo ? p.n_u : std::max(p.n_u, p.n_m));
@@ -241,7 +241,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.cstride = c->wide ? NFW : 64;
         h.col_base = 0;
         h.flag = c->flag[side];
-        h.fallback = 0;
+        h.pass = 0;
         h.partials = sc.partials;
         h.resid = sc.resid;
         h.refine = 0;
@@ -283,12 +283,16 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
                 HIP_CHECK(c, mark_begin(PROF_HSOLVE, ms));
                 h.refine = 0;
                 HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
-                // rows whose core system was singular: full-data Gram (FP32
-                // products) and solve, eq. (U)
-                h.fallback = 1;
-                HIP_CHECK(c, launch_wide_gram(h, b.pair_begin, b.pair_end, true, c->stream));
-                HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
-                h.fallback = 0;
+                // pass 1, rows whose core system was singular: full-data Gram
+                // (FP32 products) and solve, eq. (U); pass 2 (ALS_PREC_AUTO),
+                // rows too ill-conditioned for one refinement step from a bf16
+                // Gram: the Gram again with FP32 products
+                for (int pass = 1; pass <= (c->fp64res == RES_PER_ROW ? 2 : 1); ++pass) {
+                    h.pass = pass;
+                    HIP_CHECK(c, launch_wide_gram(h, b.pair_begin, b.pair_end, true, c->stream));
+                    HIP_CHECK(c, launch_wide_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                }
+                h.pass = 0;
                 HIP_CHECK(c, mark_end(ms));
                 if (c->bf16) {
                     als_ctx::Mark mr{}, m2{};
@@ -322,6 +326,14 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
             HIP_CHECK(c, mark_begin(PROF_HSOLVE, ms));
             h.refine = 0;
             HIP_CHECK(c, launch_heavy_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+            if (c->fp64res == RES_PER_ROW) {
+                // rows too ill-conditioned for one refinement step from a bf16
+                // Gram: the Gram again with FP32 products, and a new solve
+                h.pass = 2;
+                HIP_CHECK(c, launch_heavy_gram(h, b.pair_begin, b.pair_end, c->stream));
+                HIP_CHECK(c, launch_heavy_solve(h, b.slot_begin, b.slot_end, b.pair_begin, c->stream));
+                h.pass = 0;
+            }
             HIP_CHECK(c, mark_end(ms));
             if (c->bf16) {
                 // one refinement step: chunk residuals, then the correction solve
@@ -401,6 +413,7 @@ als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als
     st->n_singular_fallback = (int64_t)h[ST_FALLBACK];
     st->n_fp64_residual = (int64_t)h[ST_FP64RES];
     st->n_rows = c->side[side].n_rows;
+    st->n_fp32_gram = (int64_t)h[ST_FP32GRAM];
     return ALS_OK;
 }
 

@@ -483,6 +483,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         const int lane = opaque_lane(lane0);
         const int64_t i = a.rows[slot];
         if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
+        if (a.pass && a.flag[slot] != a.pass) continue;
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -506,20 +507,37 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         bool ok;
         if (a.keep) {
             // a refinement step follows: keep the factors for it
+            float rs = 0.f;  // |A|_inf, for the condition estimate
+#pragma unroll
+            for (int b = 0; b < NF; ++b) rs += fabsf(A[b]);
+            const float anorm = __int_as_float(wave_max_key(__float_as_int(rs)));
             int my_step;
             float r[1] = {rhs};
-            float pmin, pmax;
-            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step, pmin, pmax);
-            int need64 = 0;  // bit 16 of the kept step: FP64 residual for this row
+            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step);
+            int need64 = 0;        // bit 16 of the kept step: FP64 residual for this row
+            bool regram = false;   // ALS_PREC_AUTO: Gram again with FP32 products
             if (ok) {
                 u = lu_back(A, r, lane, my_step, L);
+                if (a.fp64res == RES_PER_ROW) {
+                    float e[1] = {lane < a.nf ? kappa_probe(lane) : 0.f};
+                    fwd_all_u<1>(std::make_integer_sequence<int, NF>{}, A, e, my_step);
+                    const float z = lu_back(A, e, lane, my_step, L);
+                    const float kest =
+                        anorm * __int_as_float(wave_max_key(__float_as_int(fabsf(z)))) * (1.f / 3.f);
+                    need64 = ((double)a.lam < FP64_LAMBDA && kest > KAPPA_FP64) ? 1 : 0;
+                    regram = a.pass == 0 && kest > KAPPA_BF16;
+                } else if (a.fp64res == RES_FP64) {
+                    need64 = 1;
+                }
+                if (!regram)
 #pragma unroll
-                for (int b = 0; b < NF; ++b) fac[b * 64 + lane] = A[b];
-                if (a.fp64res == RES_FP64) need64 = 1;
-                else if (a.fp64res == RES_PER_ROW)
-                    need64 = ((double)a.lam < FP64_LAMBDA && pmax > FP64_PIVOT_RATIO * pmin) ? 1 : 0;
+                    for (int b = 0; b < NF; ++b) fac[b * 64 + lane] = A[b];
             }
-            fac[NF * 64 + lane] = __int_as_float(ok ? (my_step | (need64 << 16)) : -1);
+            fac[NF * 64 + lane] = __int_as_float(ok && !regram ? (my_step | (need64 << 16)) : -1);
+            if (lane == 0 && a.pass == 0) {
+                a.flag[slot] = regram ? 2 : 0;
+                if (regram) atomicAdd(&a.stats[ST_FP32GRAM], 1ull);
+            }
         } else {
             ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         }
@@ -721,6 +739,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
         if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
+        if (a.pass && a.flag[slot] != a.pass) continue;
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);

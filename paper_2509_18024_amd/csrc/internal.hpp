@@ -31,11 +31,18 @@ constexpr int DEFAULT_HEAVY_N = 1024;    // light rows have degree <= this
 constexpr int DEFAULT_CHUNK = 1024;      // entries per partial Gram of a heavy row
 constexpr int64_t PAIR_CAP = 65536;      // partial systems held in scratch at once
 constexpr int64_t PAIR_CAP_WIDE = 8192;  // the same at ranks above 64 (66 KB per system)
-// Refinement residual in FP64 when the precision mode asks for it per row:
-// lambda below this and a pivot ratio max|p| / min|p| of the row's LU above
-// FP64_PIVOT_RATIO (an estimate of the system's condition number).
+// Per-row precision of the BF16 + refinement mode ALS_PREC_AUTO, from the
+// condition estimate kappa = |A|_inf |A^-1 e|_inf / |e|_inf of the row's system
+// (one extra solve with the kept LU factors, e = kappa_probe):
+//  - kappa > KAPPA_BF16 = 2^8: one refinement step from bf16-rounded products
+//    (unit roundoff 2^-8) is not expected to contract, so the row's Gram is
+//    built again with FP32 products (exact three-way split) and refactored;
+//  - lambda < FP64_LAMBDA and kappa > KAPPA_FP64 = 2^10: an FP32 residual
+//    would limit the refined row to about kappa 2^-24, above 6e-5, so its
+//    refinement residual is accumulated in FP64.
+constexpr float KAPPA_BF16 = 256.f;
 constexpr double FP64_LAMBDA = 1e-3;
-constexpr float FP64_PIVOT_RATIO = 1e3f;
+constexpr float KAPPA_FP64 = 1024.f;
 // fp64res modes of HeavyArgs
 enum Fp64Mode : int { RES_FP32 = 0, RES_FP64 = 1, RES_PER_ROW = 2 };
 
@@ -117,7 +124,15 @@ struct Side {
 constexpr int NPROF = 12;
 enum ProfSlot : int { PROF_HSELECT = 7, PROF_HGRAM = 8, PROF_HSOLVE = 9, PROF_HRESID = 10, PROF_HREFINE = 11 };
 
-enum StatSlot : int { ST_EMPTY = 0, ST_FALLBACK = 1, ST_FP64RES = 2, ST_ROWS = 3, ST_FOLDIN_EXACT = 4, NSTATS = 8 };
+enum StatSlot : int {
+    ST_EMPTY = 0,
+    ST_FALLBACK = 1,
+    ST_FP64RES = 2,
+    ST_ROWS = 3,
+    ST_FOLDIN_EXACT = 4,
+    ST_FP32GRAM = 5,
+    NSTATS = 8
+};
 
 struct SweepArgs {
     const int64_t *ptr;
@@ -169,8 +184,10 @@ struct HeavyArgs {
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
     int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // Fp64Mode of the refinement residual
-    int32_t *flag;            // wide ranks: per heavy slot, 1 = core system singular
-    int32_t fallback;         // wide ranks: pass over the flagged rows with the full data
+    int32_t *flag;            // per heavy slot: 0, or the pass that redoes the row
+    int32_t pass;             // 0: all rows; 1 (wide ranks): rows with a singular core
+                              // system, from the full data; 2 (ALS_PREC_AUTO): rows
+                              // whose Gram is built again with FP32 products
     unsigned long long *stats;
     unsigned int *queue;      // heavy-row selection counter (nullptr: grid-stride)
     // fold-in check mode (see SweepArgs); with path set, the Gram, solve and
@@ -276,7 +293,7 @@ struct als_ctx {
     bool bf16 = false;     // heavy-row Gram on bf16 MFMA + one refinement step
     int fp64res = 0;       // Fp64Mode of the refinement residual
     bool wide = false;     // 64 < n_f <= NFW: wide-rank kernels for every row
-    int32_t *flag[2] = {nullptr, nullptr};  // wide ranks: singular-system flags per heavy slot
+    int32_t *flag[2] = {nullptr, nullptr};  // per heavy slot: the pass that redoes the row
     void *temp = nullptr;
     size_t temp_bytes = 0;
     std::string err;

@@ -436,10 +436,9 @@ __device__ __forceinline__ int pivot_key(const float (&A)[NF], int lane, int my_
 // pk: with PIVOT, the wave's maximum pivot key of column J, computed by the
 // previous step as soon as column J was final (lookahead: the reduction runs
 // beside the rest of that step's update); on return, the key of column J + 1.
-// KEEP also tracks the smallest and largest |pivot| of the first nf steps.
 template <bool PIVOT, int NR, int J, bool KEEP>
 __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
-                                            int &my_step, bool &ok, int &pk, float &pmin, float &pmax) {
+                                            int &my_step, bool &ok, int &pk) {
     int p;
     bool active;
     if constexpr (PIVOT) {
@@ -451,12 +450,6 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     }
     const float piv = readlane_f(A[J], p);
     ok = ok && (J >= nf || fabsf(piv) > tol);
-    if constexpr (KEEP) {
-        if (J < nf) {
-            pmin = fminf(pmin, fabsf(piv));
-            pmax = fmaxf(pmax, fabsf(piv));
-        }
-    }
     const bool elim = active && lane != p;
     // multipliers by the hardware reciprocal (1 ulp) instead of an IEEE
     // division sequence: one uniform reciprocal per step
@@ -505,10 +498,9 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
 
 template <bool PIVOT, int NR, bool KEEP, int... J>
 __device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR],
-                                           int lane, int nf, float tol, int &my_step, bool &ok, float &pmin,
-                                           float &pmax) {
+                                           int lane, int nf, float tol, int &my_step, bool &ok) {
     int pk = PIVOT ? pivot_key<0>(A, lane, my_step) : 0;
-    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok, pk, pmin, pmax), ...);
+    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok, pk), ...);
 }
 
 // Forward elimination of a new right-hand side with kept factors: at step J
@@ -549,9 +541,7 @@ __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int la
                                         float (&x)[NR], LDS &L) {
     int my_step = NF;  // elimination step at which this lane's row was the pivot
     bool ok = true;
-    float pmin = 0.f, pmax = 0.f;  // not tracked without KEEP
-    elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok, pmin,
-                                 pmax);
+    elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
     if (!PIVOT) my_step = lane;
     if (!ok) return false;
     wave_sync();
@@ -575,17 +565,17 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
 
 // Pivoted LU that keeps its factors in A (multipliers below, U above the
 // pivots) and the lane's pivot step in my_step; returns false on a pivot of
-// the first nf steps <= tol.  pmin / pmax: smallest and largest |pivot| of
-// those steps (their ratio estimates the condition number).
-__device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lane, int nf, float tol, int &my_step,
-                                        float &pmin, float &pmax) {
+// the first nf steps <= tol.
+__device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lane, int nf, float tol, int &my_step) {
     my_step = NF;
     bool ok = true;
-    pmin = __builtin_inff();
-    pmax = 0.f;
-    elim_all_u<true, 1, true>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok, pmin, pmax);
+    elim_all_u<true, 1, true>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
     return ok;
 }
+
+// Entry a of the fixed right-hand side whose solution estimates |A^-1|: signs
+// alternate, magnitudes 1, 2, 3 in turn (|e|_inf = 3).
+__device__ __forceinline__ float kappa_probe(int a) { return (a & 1 ? -1.f : 1.f) * (float)(1 + a % 3); }
 
 // Back substitution of an eliminated right-hand side; x = component `lane`.
 template <class LDS>

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(WT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const_cast<float *>(a.other), (short)0, BUF ? (int)(a.other_rows * nf * 4) : 0, 0x00020000);
     for (int64_t p = pair_begin + blockIdx.x; p < pair_end; p += gridDim.x) {
         const int64_t slot = a.pair_slot[p];
-        if (a.fallback && a.flag[slot] == 0) continue;  // uniform over the workgroup
+        if (a.pass && a.flag[slot] != a.pass) continue;  // uniform over the workgroup
         const int chunk = a.pair_chunk[p];
         const int64_t i = a.rows[slot];
         const int64_t beg = a.ptr[i];
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(WT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
         // kept(k) <=> (key, ~k) >= (T, ~K) as unsigned 64-bit pairs
         int T = 0, K = 0x7FFFFFFF;  // every entry kept (full data)
-        if (!a.fallback && s < n) {
+        if (a.pass != 1 && s < n) {
             if (s == 0) {
                 T = 0x7FFFFFFF;
                 K = -1;
@@ -237,7 +237,10 @@ struct WideLds {
     int row_of_step[NFW];
     int piv[2];
     float pval[2];
-    int amax;  // bits of max |A| (non-negative floats order as integers)
+    float rsum[NFW];  // row sums of |A|
+    int amax;         // bits of max |A| (non-negative floats order as integers)
+    int anorm;        // bits of |A|_inf
+    int zmax;         // bits of |A^-1 e|_inf
     int ok;
 };
 
@@ -291,18 +294,14 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Factor the system in place (multipliers stored below the pivots, in the
 // eliminated rows' columns) and eliminate S.rhs with it.  step[q]: the step
 // at which row 8 bi + q was the pivot.  Returns false (uniformly) when a pivot
-// of the first nf steps is at most tol.  pmin / pmax: smallest and largest
-// |pivot| of those steps.
-__device__ __forceinline__ bool wide_lu(float (&A)[8][8], int (&step)[8], WideLds &S, int nf, float tol, float &pmin,
-                                        float &pmax) {
+// of the first nf steps is at most tol.
+__device__ __forceinline__ bool wide_lu(float (&A)[8][8], int (&step)[8], WideLds &S, int nf, float tol) {
     const int tid = threadIdx.x;
     const int bi = tid & 15, bj = tid >> 4;
     const int w = wave_index();
     const int lane = tid & 63;
 #pragma unroll
     for (int q = 0; q < 8; ++q) step[q] = NFW;
-    pmin = __builtin_inff();
-    pmax = 0.f;
 #pragma unroll 1
     for (int jb = 0; jb < NFW / 8; ++jb) {
 #pragma unroll
@@ -346,11 +345,6 @@ __device__ __forceinline__ bool wide_lu(float (&A)[8][8], int (&step)[8], WideLd
             }
             __syncthreads();
             const int p = uniform(S.piv[buf]);
-            const float apv = fabsf(S.pval[buf]);
-            if (J < nf) {
-                pmin = fminf(pmin, apv);
-                pmax = fmaxf(pmax, apv);
-            }
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (8 * bi + q == p) step[q] = J;
@@ -458,10 +452,11 @@ __device__ __forceinline__ void wide_back(const float (&A)[8][8], const int (&st
 }
 
 // One workgroup per heavy slot: the row's system from its partial systems,
-// solved (first pass), or the flagged rows again from full-data partials
-// (fallback pass).  With keep, the LU factors and each row's pivot step (bit
-// 16: refine this row with an FP64 residual) go to the row's first partial
-// slot for the refinement step; -1 there means no refinement.
+// solved (pass 0), or the rows flagged for pass 1 (singular core system,
+// full-data partials) or pass 2 (ALS_PREC_AUTO: partials with FP32 products).
+// With keep, the LU factors and each row's pivot step (bit 16: refine this row
+// with an FP64 residual) go to the row's first partial slot for the
+// refinement step; -1 there means no refinement.
 __global__ __launch_bounds__(WT) void k_wide_solve(HeavyArgs a, int64_t slot_begin, int64_t slot_end,
                                                    int64_t pair_base) {
     __shared__ WideLds S;
@@ -469,7 +464,7 @@ __global__ __launch_bounds__(WT) void k_wide_solve(HeavyArgs a, int64_t slot_beg
     const int bi = tid & 15, bj = tid >> 4;
     const int nf = a.nf;
     for (int64_t slot = slot_begin + blockIdx.x; slot < slot_end; slot += gridDim.x) {
-        if (a.fallback && a.flag[slot] == 0) continue;  // uniform
+        if (a.pass && a.flag[slot] != a.pass) continue;  // uniform
         const int64_t i = a.rows[slot];
         const int n = (int)(a.ptr[i + 1] - a.ptr[i]);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
@@ -491,9 +486,10 @@ __global__ __launch_bounds__(WT) void k_wide_solve(HeavyArgs a, int64_t slot_beg
 #pragma unroll
                 for (int q = 0; q < 8; ++q) rhs[q] += src[NFW * NFW + 8 * tid + q];
         }
-        float amax = 0.f;
+        float amax = 0.f, rs[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 8; ++q) {
+            rs[q] = 0.f;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const int r = 8 * bi + q, col = 8 * bj + c;
@@ -501,36 +497,60 @@ __global__ __launch_bounds__(WT) void k_wide_solve(HeavyArgs a, int64_t slot_beg
                 if (r >= nf) v = (r == col) ? 1.f : 0.f;  // padding: identity rows
                 A[q][c] = v;
                 amax = fmaxf(amax, fabsf(v));
+                rs[q] += fabsf(v);
             }
+        }
         if (tid == 0) {
             S.amax = 0;
+            S.anorm = 0;
+            S.zmax = 0;
             S.ok = 1;
         }
+        if (tid < NFW) S.rsum[tid] = 0.f;
         __syncthreads();
         if (tid < 16)
 #pragma unroll
             for (int q = 0; q < 8; ++q) S.rhs[8 * tid + q] = 8 * tid + q < nf ? rhs[q] : 0.f;
         atomicMax(&S.amax, __float_as_int(amax));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) atomicAdd(&S.rsum[8 * bi + q], rs[q]);
         __syncthreads();
+        if (tid < NFW) atomicMax(&S.anorm, __float_as_int(S.rsum[tid]));
         const float tol = (float)nf * 1.1920928955078125e-7f * __int_as_float(S.amax);
         int step[8];
-        float pmin, pmax;
-        const bool ok = wide_lu(A, step, S, nf, tol, pmin, pmax);
-        bool keep_fac = false;
+        const bool ok = wide_lu(A, step, S, nf, tol);  // (its barriers publish S.anorm)
+        bool keep_fac = false, regram = false;
         int need64 = 0;
         if (ok) {
             wide_back(A, step, S);
-            keep_fac = a.keep && !a.fallback;
-            if (a.fp64res == RES_FP64) need64 = 1;
-            else if (a.fp64res == RES_PER_ROW)
-                need64 = ((double)a.lam < FP64_LAMBDA && pmax > FP64_PIVOT_RATIO * pmin) ? 1 : 0;
+            if (tid < nf) a.out[i * nf + tid] = S.x[tid];
+            keep_fac = a.keep && a.pass != 1;
+            if (keep_fac && a.fp64res == RES_PER_ROW) {
+                // condition estimate |A|_inf |A^-1 e|_inf / |e|_inf
+                __syncthreads();
+                if (tid < NFW) S.rhs[tid] = tid < nf ? kappa_probe(tid) : 0.f;
+                wide_forward(A, step, S);
+                wide_back(A, step, S);
+                if (tid < nf) atomicMax(&S.zmax, __float_as_int(fabsf(S.x[tid])));
+                __syncthreads();
+                const float kest = __int_as_float(S.anorm) * __int_as_float(S.zmax) * (1.f / 3.f);
+                need64 = ((double)a.lam < FP64_LAMBDA && kest > KAPPA_FP64) ? 1 : 0;
+                regram = a.pass == 0 && kest > KAPPA_BF16;
+                keep_fac = !regram;
+            } else if (a.fp64res == RES_FP64) {
+                need64 = 1;
+            }
+        } else if (tid < nf) {
+            a.out[i * nf + tid] = 0.f;
         }
-        if (!a.fallback && tid == 0) {
-            const bool flagged = !ok && s < n;  // singular core system: full-data pass follows
-            a.flag[slot] = flagged ? 1 : 0;
-            if (flagged) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
+        if (a.pass == 0 && tid == 0) {
+            // pass 1: singular core system, solved again from the full data;
+            // pass 2: Gram again with FP32 products
+            const bool singular = !ok && s < n;
+            a.flag[slot] = singular ? 1 : regram ? 2 : 0;
+            if (singular) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
+            if (regram) atomicAdd(&a.stats[ST_FP32GRAM], 1ull);
         }
-        if (tid < nf) a.out[i * nf + tid] = ok ? S.x[tid] : 0.f;
         if (a.keep) {
             if (keep_fac) {
 #pragma unroll
