@@ -67,6 +67,13 @@ def lib():
                                            I32P]
         L.ora_objective.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, I64P, I32P,
                                     F32P, F64P, F64P, ctypes.c_double, F64P]
+        U8P = ctypes.POINTER(ctypes.c_uint8)
+        L.ora_global_select.argtypes = [ctypes.c_int64, ctypes.c_int32, F64P, ctypes.c_int64, U8P]
+        L.ora_masked_row.restype = ctypes.c_int
+        L.ora_masked_row.argtypes = [ctypes.c_int64, ctypes.c_int32, F64P, U8P, F64P, ctypes.c_double, F64P]
+        L.ora_fast_half_sweep.argtypes = [ctypes.c_int64, ctypes.c_int32, I64P, I32P, F32P, ctypes.c_int64,
+                                          F64P, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, F64P, I64P]
         _lib = L
     return _lib
 
@@ -173,6 +180,43 @@ def core_select_rows(rows, row_ptr, col_idx, other, num, den, min_keep):
                                _p(O, F64P), int(num), int(den), int(min_keep),
                                _p(sel_ptr, I64P), _p(sel, I32P))
     return sel_ptr, sel
+
+
+def global_select(other, num, den, min_keep):
+    """Fast variant of Core-ALS (Section 3): CES applied once to the whole factor
+    matrix `other` at budget(n_other).  Returns the kept mask (n_other x nf, uint8)."""
+    O = _c(other, np.float64)
+    n, nf = O.shape
+    keep = np.zeros((n, nf), np.uint8)
+    lib().ora_global_select(n, nf, _p(O, F64P), budget(n, num, den, min_keep),
+                            keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return keep
+
+
+def masked_row(X, K, y, lam):
+    """One regression on the sketch X* = K * X (eq. core_ui).  Returns (u, status)."""
+    X = _c(X, np.float64)
+    K = _c(K, np.uint8)
+    y = _c(y, np.float64)
+    n, nf = X.shape
+    u = np.zeros(nf, np.float64)
+    st = lib().ora_masked_row(n, nf, _p(X, F64P), K.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                              _p(y, F64P), float(lam), _p(u, F64P))
+    return u, st
+
+
+def fast_half_sweep(row_ptr, col_idx, val, other, lam, num, den, min_keep):
+    """One half-sweep of the fast variant (Section 3): the global sketch of
+    `other`, then every row's regression on it.  Returns (out, stats)."""
+    rp, ci, v = _c(row_ptr, np.int64), _c(col_idx, np.int32), _c(val, np.float32)
+    O = _c(other, np.float64)
+    n_rows = len(rp) - 1
+    nf = O.shape[1]
+    out = np.zeros((n_rows, nf), np.float64)
+    st = np.zeros(2, np.int64)
+    lib().ora_fast_half_sweep(n_rows, nf, _p(rp, I64P), _p(ci, I32P), _p(v, F32P), O.shape[0], _p(O, F64P),
+                              float(lam), int(num), int(den), int(min_keep), _p(out, F64P), _p(st, I64P))
+    return out, st
 
 
 def objective(row_ptr, col_idx, val, U, M, lam):

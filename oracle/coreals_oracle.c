@@ -17,6 +17,10 @@
  *  - the core estimator u = (X*^T X + lambda n_i E)^-1 X*^T y
  *                                                          (Section 3, eq. core_ui/core_mj)
  *  - one half-sweep of Core-ALS over all rows              (Section 3, Algorithm 2)
+ *  - the fast variant: CES once per half-sweep on the whole factor matrix of
+ *    the other side, each row regressing on that global sketch
+ *                                                          (Section 3, the paragraph
+ *                                                             after Algorithm 2)
  *
  * Readings where the paper leaves a choice open:
  *  - ties in the top-s are broken by smaller position first;
@@ -396,4 +400,104 @@ void ora_objective(int64_t n_u, int64_t n_m, int32_t nf, const int64_t *row_ptr,
     out[1] = sse;
     out[2] = nnz > 0 ? sqrt(sse / (double)nnz) : 0.0;
     out[3] = rr > 0.0 ? sqrt(sse) / sqrt(rr) : 0.0;
+}
+
+/* ------------------------------------------------------------------------
+ * Fast variant of Core-ALS (Section 3, the paragraph and figure after
+ * Algorithm 2; its details are in the paper's appendix, which is not part of
+ * the text).  Reading: before each half-sweep, CES (Algorithm 1) is applied
+ * once to the whole factor matrix of the other side, at the rate r, instead of
+ * to every row's slice; each regression then uses the rows of that global
+ * sketch, X* = (global mask) applied to the row's design matrix.  The per-row
+ * number of kept entries therefore only follows r on average, as the paper
+ * says of this variant.
+ * ---------------------------------------------------------------------- */
+
+/* keep[j * nf + a] = 1 for the s = budget(n_other) entries of column a with
+ * the largest |other[j][a]| (ties: the smaller j), 0 elsewhere. */
+void ora_global_select(int64_t n_other, int32_t nf, const double *other, int64_t s, uint8_t *keep) {
+    for (int64_t e = 0; e < n_other * (int64_t)nf; ++e) keep[e] = 0;
+    if (s <= 0) return;
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)nf * (size_t)s);
+    ora_select(n_other, nf, other, s, pos);
+    for (int32_t a = 0; a < nf; ++a)
+        for (int64_t t = 0; t < s; ++t) keep[(int64_t)pos[a * s + t] * nf + a] = 1;
+    free(pos);
+}
+
+/* One regression with a given sketch mask K (n x nf): (X*^T X + lambda n E) u
+ * = X*^T y, X* = K (elementwise) X, the system of eq. core_ui.  Status as
+ * ora_core_row: 1 empty row, 2 singular system replaced by eq. (U), 3 singular
+ * with every entry kept (the system is eq. (U) itself; u = 0). */
+int ora_masked_row(int64_t n, int32_t nf, const double *X, const uint8_t *K, const double *y, double lam,
+                   double *u) {
+    if (n == 0) {
+        for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+        return 1;
+    }
+    double *A = (double *)calloc((size_t)nf * nf, sizeof(double));
+    double *b = (double *)calloc((size_t)nf, sizeof(double));
+    int all_kept = 1;
+    for (int32_t a = 0; a < nf; ++a) {
+        for (int64_t k = 0; k < n; ++k) {
+            if (!K[k * nf + a]) {
+                all_kept = 0;
+                continue;
+            }
+            double xa = X[k * nf + a];
+            for (int32_t c = 0; c < nf; ++c) A[a * nf + c] += xa * X[k * nf + c];
+            b[a] += xa * y[k];
+        }
+        A[a * nf + a] += lam * (double)n;
+    }
+    double amax = 0.0;
+    for (int64_t e = 0; e < (int64_t)nf * nf; ++e) amax = fmax(amax, fabs(A[e]));
+    int status = 0;
+    if (ora_gepp(nf, A, b, (double)nf * ldexp(1.0, -52) * amax)) {
+        if (!all_kept) {
+            ora_full_row(n, nf, X, y, lam, u);
+            status = 2;
+        } else {
+            for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+            status = 3;
+        }
+    } else {
+        for (int32_t a = 0; a < nf; ++a) u[a] = b[a];
+    }
+    free(A);
+    free(b);
+    return status;
+}
+
+/* One half-sweep of the fast variant: the global sketch of `other`
+ * (n_other x nf) at budget(n_other), then every row's regression on it.
+ * stats[0] empty rows, stats[1] singular systems replaced by eq. (U). */
+void ora_fast_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr, const int32_t *col_idx,
+                         const float *val, int64_t n_other, const double *other, double lam, int64_t num,
+                         int64_t den, int64_t min_keep, double *out, int64_t *stats) {
+    uint8_t *keep = (uint8_t *)malloc((size_t)(n_other > 0 ? n_other : 1) * nf);
+    ora_global_select(n_other, nf, other, ora_budget(n_other, num, den, min_keep), keep);
+    int64_t n_empty = 0, n_fallback = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_empty, n_fallback)
+    for (int64_t i = 0; i < n_rows; ++i) {
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        uint8_t *K = (uint8_t *)malloc((size_t)(n > 0 ? n : 1) * nf);
+        ora_gather(beg, n, nf, col_idx, val, other, X, y);
+        for (int64_t k = 0; k < n; ++k)
+            for (int32_t a = 0; a < nf; ++a) K[k * nf + a] = keep[(int64_t)col_idx[beg + k] * nf + a];
+        int st = ora_masked_row(n, nf, X, K, y, lam, out + i * nf);
+        if (st == 1) n_empty++;
+        if (st == 2) n_fallback++;
+        free(X);
+        free(y);
+        free(K);
+    }
+    free(keep);
+    if (stats) {
+        stats[0] = n_empty;
+        stats[1] = n_fallback;
+    }
 }

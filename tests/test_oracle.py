@@ -381,3 +381,106 @@ def test_singular_core_system_exact_fallback(ora):
     assert cnt[1] == 1 and np.all(out[1] == 0.0)
     np.testing.assert_allclose(out[0], np.linalg.lstsq(X, vals[:12].astype(np.float64), rcond=None)[0],
                                rtol=1e-10)
+
+
+# ---------------------------------------------------------------- fast variant
+# (Section 3, the paragraph after Algorithm 2: CES once per half-sweep on the
+# whole factor matrix of the other side; each row regresses on that sketch)
+
+def _ties_matrix(rng, n, nf):
+    """Factor entries from a small pool, so that many |x| tie exactly."""
+    pool = np.array([0.0, -0.0, 0.5, -0.5, 0.25, 1.0, -1.0, 2.0, -2.0, 1e-40], np.float64)
+    return rng.choice(pool, size=(n, nf))
+
+
+@pytest.mark.parametrize("num,den,min_keep", [(1, 10, 1), (1, 4, 0), (3, 7, 1), (1, 1000, 0)])
+def test_global_select_pinned_by_bruteforce(ora, num, den, min_keep):
+    """The global sketch keeps, per column, the budget(n_other) entries of the
+    largest |x| with smaller row index first on ties: an independent key sort
+    per column, on random values and on values with exact ties."""
+    rng = np.random.default_rng(num * 100 + den)
+    for O in (rng.normal(0, 1, (97, 6)), _ties_matrix(rng, 120, 5)):
+        keep = ora.global_select(O, num, den, min_keep)
+        s = ora.budget(O.shape[0], num, den, min_keep)
+        assert np.array_equal(keep.astype(bool), brute_mask(O, s))
+        assert np.all(keep.sum(axis=0) == s)
+
+
+def _fast_dense(row_ptr, col_idx, val, O, lam, num, den, min_keep):
+    """Brute force: the global mask from a key sort, then each row's sketch
+    built explicitly and solved with LAPACK."""
+    s = min(O.shape[0], max(min_keep, O.shape[0] * num // den))
+    G = brute_mask(O, s)
+    out = np.zeros((len(row_ptr) - 1, O.shape[1]))
+    for i in range(len(row_ptr) - 1):
+        cols = col_idx[row_ptr[i]:row_ptr[i + 1]]
+        if len(cols) == 0:
+            continue
+        X = O[cols]
+        Xs = np.where(G[cols], X, 0.0)
+        y = val[row_ptr[i]:row_ptr[i + 1]].astype(np.float64)
+        A = Xs.T @ X + lam * len(cols) * np.eye(O.shape[1])
+        out[i] = np.linalg.solve(A, Xs.T @ y)
+    return out
+
+
+@pytest.mark.parametrize("num,den", [(1, 10), (1, 4), (1, 2)])
+def test_fast_half_sweep_vs_dense_bruteforce(ora, num, den):
+    p = synth.random_problem(61 + den, 70, 50, 6, 0.3, budget=(num, den))
+    O = p.M0.astype(np.float64)
+    out, st = ora.fast_half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, num, den, 1)
+    ref = _fast_dense(p.row_ptr, p.col_idx, p.val, O, p.lam, num, den, 1)
+    assert st[1] == 0
+    assert np.allclose(out, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_fast_full_budget_is_exact_als(ora):
+    """r = 1 keeps every entry of the global sketch: the fast half-sweep is the
+    full-data half-sweep (eq. (U))."""
+    p = synth.random_problem(71, 60, 40, 5, 0.3, budget=(1, 1))
+    O = p.M0.astype(np.float64)
+    fast, _ = ora.fast_half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, 1, 1, 1)
+    full, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, 1, 1, 1)
+    assert np.allclose(fast, full, rtol=1e-11, atol=1e-13)
+
+
+def test_fast_lambda_zero_fixed_point(ora):
+    """lambda = 0 and noiseless ratings y = X u*: X*^T X u* = X*^T y for any
+    sketch, so every row whose sketch system is invertible returns u* (the
+    symmetric X*^T X* form would not)."""
+    rng = np.random.default_rng(72)
+    n_u, n_m, nf = 30, 200, 4
+    O = rng.normal(0, 1, (n_m, nf))
+    Ut = rng.normal(0, 1, (n_u, nf))
+    rows = [np.sort(rng.choice(n_m, size=60, replace=False)) for _ in range(n_u)]
+    rp = np.zeros(n_u + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = np.concatenate([O[r] @ Ut[i] for i, r in enumerate(rows)]).astype(np.float32)
+    # float32 ratings: compare against the exact solution for those ratings
+    out, st = ora.fast_half_sweep(rp, ci, val, O, 0.0, 1, 4, 1)
+    keep = ora.global_select(O, 1, 4, 1).astype(bool)
+    for i, r in enumerate(rows):
+        X = O[r]
+        Xs = np.where(keep[r], X, 0.0)
+        y = val[rp[i]:rp[i + 1]].astype(np.float64)
+        u_exact = np.linalg.solve(Xs.T @ X, Xs.T @ y)
+        assert np.allclose(out[i], u_exact, rtol=1e-9, atol=1e-9)
+        assert np.allclose(out[i], Ut[i], rtol=1e-5, atol=1e-5)
+        Xss = Xs.T @ Xs
+        assert not np.allclose(np.linalg.solve(Xss, Xs.T @ y), Ut[i], rtol=1e-3, atol=1e-3)
+
+
+def test_fast_masked_row_singular_fallback(ora):
+    """A sketch with an all-zero column at lambda = 0 makes the system singular:
+    the row takes eq. (U) (least squares on all its entries), status 2."""
+    rng = np.random.default_rng(73)
+    X = rng.normal(0, 1, (20, 3))
+    y = rng.normal(0, 1, 20)
+    K = np.ones((20, 3), np.uint8)
+    K[:, 1] = 0
+    u, st = ora.masked_row(X, K, y, 0.0)
+    assert st == 2
+    assert np.allclose(u, np.linalg.lstsq(X, y, rcond=None)[0], rtol=1e-10)
+    u1, st1 = ora.masked_row(X, np.ones((20, 3), np.uint8), y, 0.0)
+    assert st1 == 0 and np.allclose(u1, np.linalg.lstsq(X, y, rcond=None)[0], rtol=1e-10)
