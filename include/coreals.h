@@ -102,6 +102,14 @@ typedef struct {
     int32_t light_blocks;        /* grid of the persistent light-row kernels, whose
                                     wavefronts take rows from an atomic counter;
                                     0 = one row per wavefront */
+    const int64_t *col_ptr;      /* optional column view (CSC) of the same R, device:
+                                    col_ptr int64[n_m+1], row_idx int32[nnz] strictly
+                                    increasing inside a column, val_t float32[nnz];
+                                    all NULL = built by als_init in the workspace.
+                                    Checked like the CSR (not against it); kept by
+                                    pointer until als_destroy                       */
+    const int32_t *row_idx;
+    const float *val_t;
 } als_problem;
 
 typedef struct {
@@ -112,6 +120,10 @@ typedef struct {
     int64_t n_rows;              /* rows solved in this half-sweep                */
     int64_t n_fp32_gram;         /* ALS_PREC_AUTO: rows whose Gram was built again
                                     with FP32 products (condition estimate)       */
+    double max_rel_residual;     /* BF16 modes: largest relative residual
+                                    |b - A u0| / |b| of a refined row's first
+                                    solution u0 (A u = b its system); 0 when no
+                                    row is refined                                */
 } als_sweep_stats;
 
 typedef struct {

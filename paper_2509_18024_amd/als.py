@@ -36,7 +36,7 @@ class CoreALS:
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
                  light_blocks: int = 0, graphs: bool = False, users_only: bool = False,
-                 generic_gathers: bool = False):
+                 generic_gathers: bool = False, csc=None):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -60,6 +60,14 @@ class CoreALS:
         p.heavy_chunk = int(heavy_chunk)
         p.heavy_pair_cap = int(heavy_pair_cap)
         p.light_blocks = int(light_blocks)
+        if csc is not None:
+            # the caller's column view of the same R (col_ptr, row_idx, val_t)
+            cp, ri, vt = csc
+            _need(cp, torch.int64, n_m + 1, "col_ptr")
+            _need(ri, torch.int32, nnz, "row_idx")
+            _need(vt, torch.float32, nnz, "val_t")
+            p.col_ptr, p.row_idx, p.val_t = cp.data_ptr(), ri.data_ptr(), vt.data_ptr()
+            self._keep = self._keep + (cp, ri, vt)
         size = capi.als_workspace_size(p)
         if size == 0:
             raise capi.ALSError(capi.ALS_E_ARG, "invalid problem sizes")

@@ -36,13 +36,14 @@ class als_problem(ctypes.Structure):
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("heavy_min_degree", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
         ("heavy_pair_cap", ctypes.c_int32), ("light_blocks", ctypes.c_int32),
+        ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p), ("val_t", ctypes.c_void_p),
     ]
 
 
 class als_sweep_stats(ctypes.Structure):
     _fields_ = [("n_empty", ctypes.c_int64), ("n_singular_fallback", ctypes.c_int64),
                 ("n_fp64_residual", ctypes.c_int64), ("n_rows", ctypes.c_int64),
-                ("n_fp32_gram", ctypes.c_int64)]
+                ("n_fp32_gram", ctypes.c_int64), ("max_rel_residual", ctypes.c_double)]
 
 
 class als_objective(ctypes.Structure):

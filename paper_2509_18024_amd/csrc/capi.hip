@@ -94,11 +94,13 @@ int64_t pair_bound(const als_problem &p, int64_t n_rows) {
 Layout carve(const als_problem &p, void *base) {
     Carve c{reinterpret_cast<char *>(base), 0, 0};
     Layout L;
-    // ALS_USERS_ONLY: no column view and no items-side schedule
+    // ALS_USERS_ONLY: no column view and no items-side schedule; a column
+    // view given by the caller is not built either
     const bool uo = (p.flags & ALS_USERS_ONLY) != 0;
-    L.col_ptr = c.take<int64_t>(uo ? 1 : (size_t)p.n_m + 1);
-    L.row_idx = c.take<int32_t>(uo ? 0 : (size_t)p.nnz);
-    L.val_t = c.take<float>(uo ? 0 : (size_t)p.nnz);
+    const bool own_csc = !uo && !p.col_ptr;
+    L.col_ptr = c.take<int64_t>(own_csc ? (size_t)p.n_m + 1 : 1);
+    L.row_idx = c.take<int32_t>(own_csc ? (size_t)p.nnz : 0);
+    L.val_t = c.take<float>(own_csc ? (size_t)p.nnz : 0);
     L.perm_u = c.take<int32_t>((size_t)p.n_u);
     L.perm_m = c.take<int32_t>(uo ? 0 : (size_t)p.n_m);
     L.stats = c.take<unsigned long long>(NSTATS);
@@ -109,7 +111,7 @@ Layout carve(const als_problem &p, void *base) {
     L.obj_partials = c.take<double>((size_t)5 * objective_blocks());
     L.obj_out = c.take<double>(4);
     L.partials = c.take<float>((size_t)pair_cap_of(p) * slot_floats(p));
-    L.resid = c.take<double>((size_t)pair_cap_of(p) * 128);
+    L.resid = c.take<double>((size_t)pair_cap_of(p) * 2 * cut_stride(p));
     // core-elements runs: top 16 bits of each |x| of the fixed factor
     // matrix, read by the first two selection passes
     const int64_t other_max = uo ? p.n_m : std::max(p.n_u, p.n_m);
@@ -124,7 +126,7 @@ Layout carve(const als_problem &p, void *base) {
         L.side[sd].cutK = c.take<int32_t>((size_t)hb * cut_stride(p));
         L.side[sd].flag = c.take<int32_t>((size_t)hb);
     }
-    size_t tb = uo ? 0 : csc_temp_bytes(p.nnz, p.n_m);
+    size_t tb = own_csc ? csc_temp_bytes(p.nnz, p.n_m) : 0;
     size_t tp = perm_temp_bytes(uo ? p.n_u : std::max(p.n_u, p.n_m));
     L.temp_bytes = tb > tp ? tb : tp;
     L.temp = c.take<char>(L.temp_bytes);
@@ -414,6 +416,9 @@ als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als
     st->n_fp64_residual = (int64_t)h[ST_FP64RES];
     st->n_rows = c->side[side].n_rows;
     st->n_fp32_gram = (int64_t)h[ST_FP32GRAM];
+    double mr;
+    std::memcpy(&mr, &h[ST_MAXRES], sizeof(mr));
+    st->max_rel_residual = mr;
     return ALS_OK;
 }
 
@@ -446,6 +451,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         return fail(nullptr, ALS_E_ARG, "unknown precision mode%s");
     if (!p->row_ptr || (p->nnz > 0 && (!p->col_idx || !p->val)))
         return fail(nullptr, ALS_E_ARG, "NULL CSR pointer%s");
+    if (p->col_ptr && (p->nnz > 0 && (!p->row_idx || !p->val_t)))
+        return fail(nullptr, ALS_E_ARG, "col_ptr given without row_idx and val_t%s");
     Layout probe = carve(*p, nullptr);
     if (!p->workspace || p->workspace_bytes < probe.total)
         return fail(nullptr, ALS_E_NOMEM, "workspace too small (see als_workspace_size)%s");
@@ -455,9 +462,10 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->p = *p;
     c->stream = reinterpret_cast<hipStream_t>(p->stream);
     Layout L = carve(*p, p->workspace);
-    c->col_ptr = L.col_ptr;
-    c->row_idx = L.row_idx;
-    c->val_t = L.val_t;
+    const bool given_csc = p->col_ptr && !(p->flags & ALS_USERS_ONLY);
+    c->col_ptr = given_csc ? const_cast<int64_t *>(p->col_ptr) : L.col_ptr;
+    c->row_idx = given_csc ? const_cast<int32_t *>(p->row_idx) : L.row_idx;
+    c->val_t = given_csc ? const_cast<float *>(p->val_t) : L.val_t;
     c->stats = L.stats;
     c->queues = L.queues;
     c->light_blocks = p->light_blocks;
@@ -504,10 +512,20 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (flags & 3) return bail(ALS_E_INDEX, "row_ptr or col_idx invalid (range, order or repeats)");
     if (flags & 4) return bail(ALS_E_VALUE, "NaN or Inf among the ratings");
 
-    // 2. column view
-    if (!c->users_only)
+    // 2. column view: built, or the caller's (checked as the CSR is: pointers
+    // monotone from 0 to nnz, row indices in range and strictly increasing)
+    if (given_csc) {
+        INIT_HIP(hipMemsetAsync(L.err_flags, 0, sizeof(int) * 4, s));
+        INIT_HIP(launch_validate(p->n_m, p->n_u, p->nnz, p->col_ptr, p->row_idx, p->val_t,
+                                 (p->flags & ALS_VALIDATE) ? 1 : 0, L.err_flags, s));
+        INIT_HIP(hipMemcpyAsync(&flags, L.err_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        INIT_HIP(hipStreamSynchronize(s));
+        if (flags & 3) return bail(ALS_E_INDEX, "col_ptr or row_idx invalid (range, order or repeats)");
+        if (flags & 4) return bail(ALS_E_VALUE, "NaN or Inf among the column view's ratings");
+    } else if (!c->users_only) {
         INIT_HIP(build_csc(p->n_u, p->n_m, p->nnz, p->row_ptr, p->col_idx, p->val, L.col_ptr, L.row_idx, L.val_t,
                            L.temp, s));
+    }
 
     // 3. schedules
     Side &U = c->side[0];
@@ -520,9 +538,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     Side &M = c->side[1];
     M.n_rows = c->users_only ? 0 : p->n_m;
     M.n_other = p->n_u;
-    M.ptr = L.col_ptr;
-    M.idx = L.row_idx;
-    M.val = L.val_t;
+    M.ptr = c->col_ptr;
+    M.idx = c->row_idx;
+    M.val = c->val_t;
     M.perm = L.perm_m;
     int64_t host_counts[2 * NCLASS] = {};
     int64_t host_max[2] = {};

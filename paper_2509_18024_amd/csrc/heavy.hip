@@ -581,11 +581,17 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_refine(HeavyArgs a, int64_t 
 #pragma unroll
         for (int b = 0; b < NF; ++b) A[b] = fac[b * 64 + lane];
         const float u0 = lane < a.nf ? a.out[i * a.nf + lane] : 0.f;
-        double rho = 0.0;
-        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p)
-            rho += a.resid[(p - pair_base) * 64 + lane];
+        double rho = 0.0, bsum = 0.0;
+        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p) {
+            rho += a.resid[(p - pair_base) * 128 + lane];
+            bsum += a.resid[(p - pair_base) * 128 + 64 + lane];
+        }
         rho -= (double)a.lam * (double)n * (double)u0;
         if (lane >= a.nf) rho = 0.0;
+        // relative residual |b - A u0| / |b| of the first solution
+        const double rel = rel_residual(rho, bsum, lane, a.nf);
+        if (lane == 0 && rel <= 1e300)
+            atomicMax(&a.stats[ST_MAXRES], (unsigned long long)__double_as_longlong(rel));
         float r[1] = {(float)rho};
         fwd_all_u<1>(std::make_integer_sequence<int, NF>{}, A, r, my_step);
         const float d = lu_back(A, r, lane, my_step, L);
@@ -906,6 +912,7 @@ template <typename acc_t>
 __device__ __forceinline__ void heavy_resid_pair(const HeavyArgs &a, WaveLds &L, RowCtx &r, const Cut &c, int chunk,
                                                  int n, int64_t p, int64_t pair_begin, int lane) {
     acc_t acc = 0;
+    double bs = 0.0;  // the chunk's share of b = X*^T y
     const int kb = chunk * a.chunk;
     const int ke = min(n, kb + a.chunk);
     for (int k0 = kb; k0 < ke; k0 += CK) {
@@ -928,11 +935,15 @@ __device__ __forceinline__ void heavy_resid_pair(const HeavyArgs &a, WaveLds &L,
         wave_sync();
         for (int kk = 0; kk < mrows; ++kk) {
             const float x = L.X[kk][lane];
-            if (kept(c, key_of(x), k0 + kk)) acc += (acc_t)x * (acc_t)L.rres[kk];
+            if (kept(c, key_of(x), k0 + kk)) {
+                acc += (acc_t)x * (acc_t)L.rres[kk];
+                bs += (double)x * (double)L.y[kk];
+            }
         }
         wave_sync();
     }
-    a.resid[(p - pair_begin) * 64 + lane] = (double)acc;
+    a.resid[(p - pair_begin) * 128 + lane] = (double)acc;
+    a.resid[(p - pair_begin) * 128 + 64 + lane] = bs;
 }
 
 __global__ __launch_bounds__(WPB * 64) void k_heavy_resid(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {

@@ -131,6 +131,7 @@ enum StatSlot : int {
     ST_ROWS = 3,
     ST_FOLDIN_EXACT = 4,
     ST_FP32GRAM = 5,
+    ST_MAXRES = 6,  // bits of the largest relative refinement residual (non-negative double)
     NSTATS = 8
 };
 
@@ -180,7 +181,8 @@ struct HeavyArgs {
     int32_t cstride;          // cut entries per row: 64, or NFW at ranks above 64
     int32_t col_base;         // selection: the launch ranks columns col_base .. + 63
     float *partials;
-    double *resid;            // [pair_cap * 128] refinement / check residual partials
+    double *resid;            // [pair_cap * 2 * cut stride]: per pair, residual and
+                              // right-hand side shares (refinement, fold-in check)
     int32_t refine;           // solve: 0 first solve, 1 apply the refinement step
     int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // Fp64Mode of the refinement residual

@@ -72,7 +72,7 @@ als_status half_sweep_noalloc(als_ctx *c, int side, const float *other, float *o
     if (side != 0 && side != 1) return set_error(c, ALS_E_ARG, "side must be 0 or 1");
     // partial systems of 65 x 64 floats (ranks up to 64) or 129 x 128 (above)
     const int64_t slot = c->wide ? (int64_t)(NFW + 1) * NFW : (int64_t)(NF + 1) * 64;
-    if (c->pair_cap * slot > NA_PAIR_CAP * (NF + 1) * 64)
+    if (c->pair_cap * slot > NA_PAIR_CAP * (NF + 1) * 64 || c->pair_cap * 2 * (c->wide ? NFW : 64) > NA_PAIR_CAP * 128)
         return set_error(c, ALS_E_ARG,
                          "half_sweep_noalloc: the context's heavy_pair_cap exceeds the partial systems of the "
                          "library's scratch array; create the context with heavy_pair_cap <= 1024 (n_f <= 64) "

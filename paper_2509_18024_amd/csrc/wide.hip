@@ -238,6 +238,8 @@ struct WideLds {
     int piv[2];
     float pval[2];
     float rsum[NFW];  // row sums of |A|
+    double rr[NFW];   // refinement: squares of the residual and right-hand side
+    double bb[NFW];
     int amax;         // bits of max |A| (non-negative floats order as integers)
     int anorm;        // bits of |A|_inf
     int zmax;         // bits of |A^-1 e|_inf
@@ -595,13 +597,28 @@ __global__ __launch_bounds__(WT) void k_wide_refine(HeavyArgs a, int64_t slot_be
             const int r = tid;
             S.row_of_step[__float_as_int(fac[NFW * NFW + r]) & 0xFFFF] = r;
             u0 = r < nf ? a.out[i * nf + r] : 0.f;
-            double rho = 0.0;
-            for (int64_t pp = a.pair_off[slot]; pp < a.pair_off[slot + 1]; ++pp)
-                rho += a.resid[(pp - pair_base) * NFW + r];
+            double rho = 0.0, bsum = 0.0;
+            for (int64_t pp = a.pair_off[slot]; pp < a.pair_off[slot + 1]; ++pp) {
+                rho += a.resid[(pp - pair_base) * 2 * NFW + r];
+                bsum += a.resid[(pp - pair_base) * 2 * NFW + NFW + r];
+            }
             rho -= (double)a.lam * (double)n * (double)u0;
-            S.rhs[r] = r < nf ? (float)rho : 0.f;
+            if (r >= nf) rho = bsum = 0.0;
+            S.rhs[r] = (float)rho;
+            S.rr[r] = rho * rho;
+            S.bb[r] = bsum * bsum;
         }
         __syncthreads();
+        if (tid == 0) {
+            // relative residual |b - A u0| / |b| of the first solution
+            double rr = 0.0, bb = 0.0;
+            for (int r = 0; r < NFW; ++r) {
+                rr += S.rr[r];
+                bb += S.bb[r];
+            }
+            if (bb > 0.0)
+                atomicMax(&a.stats[ST_MAXRES], (unsigned long long)__double_as_longlong(sqrt(rr / bb)));
+        }
         wide_forward(A, step, S);
         wide_back(A, step, S);
         if (tid < nf) a.out[i * nf + tid] = u0 + S.x[tid];
@@ -620,6 +637,7 @@ struct WideResLds {
     float u[NFW];
     double r[64];
     double half[NFW];
+    double bhalf[NFW];
 };
 
 template <typename acc_t>
@@ -636,6 +654,7 @@ __device__ __forceinline__ void wide_resid_row(const HeavyArgs &a, WideResLds &L
     const int kb = a.pair_chunk[p] * a.chunk;
     const int ke = min(n, kb + a.chunk);
     acc_t acc = 0;
+    double bs = 0.0;  // the chunk's share of b = X*^T y
     for (int k0 = kb; k0 < ke; k0 += 64) {
         const int m = min(64, ke - k0);
         __syncthreads();
@@ -655,13 +674,23 @@ __device__ __forceinline__ void wide_resid_row(const HeavyArgs &a, WideResLds &L
         __syncthreads();
         for (int k = half * 32; k < half * 32 + 32 && k < m; ++k) {
             const float x = L.X[k][col];
-            if (kept(c, key_of(x), k0 + k)) acc += (acc_t)x * (acc_t)L.r[k];
+            if (kept(c, key_of(x), k0 + k)) {
+                acc += (acc_t)x * (acc_t)L.r[k];
+                bs += (double)x * (double)L.y[k];
+            }
         }
     }
     __syncthreads();
-    if (half == 1) L.half[col] = (double)acc;
+    if (half == 1) {
+        L.half[col] = (double)acc;
+        L.bhalf[col] = bs;
+    }
     __syncthreads();
-    if (half == 0) a.resid[(p - pair_begin) * NFW + col] = col < nf ? (double)acc + L.half[col] : 0.0;
+    if (half == 0) {
+        double *dst = a.resid + (p - pair_begin) * 2 * NFW;
+        dst[col] = col < nf ? (double)acc + L.half[col] : 0.0;
+        dst[NFW + col] = col < nf ? bs + L.bhalf[col] : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(WT) void k_wide_resid(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {

@@ -705,3 +705,56 @@ def test_graph_replay_and_persistent_queue_match_eager(ora):
         assert rel_fro(Ug.cpu().numpy(), Uo) <= 1e-4
         eager.close()
         graph.close()
+
+
+@gpu
+def test_caller_column_view_matches_built(ora):
+    """A column view given by the caller (als_problem.col_ptr/row_idx/val_t)
+    gives the same factors as the one als_init builds; an invalid one is
+    rejected with ALS_E_INDEX."""
+    import torch
+    from paper_2509_18024_amd import capi
+    from paper_2509_18024_amd.als import CoreALS
+    p = synth.random_problem(17, 200, 300, 64, 0.2, budget=(1, 10), heavy_rows=(2,))
+    cp, ri, vt = ora.transpose(p.n_u, p.n_m, p.row_ptr, p.col_idx, p.val)
+    csc = tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (cp, ri, vt))
+    a = make_als(p, heavy_min_degree=64)
+    b = make_als(p, heavy_min_degree=64, csc=csc)
+    U = torch.from_numpy(Uo_of(ora, p).astype(np.float32)).cuda()
+    Ma, Mb = a.half_sweep_items(U), b.half_sweep_items(U)
+    torch.cuda.synchronize()
+    assert torch.equal(Ma, Mb)
+    oa, ob = a.objective(U, Ma), b.objective(U, Mb)
+    assert oa == ob
+    bad = ri.copy()
+    bad[1], bad[0] = bad[0], bad[1]  # column 0 no longer increasing (if it has 2 entries)
+    assert cp[1] >= 2
+    with pytest.raises(capi.ALSError) as ei:
+        make_als(p, csc=(csc[0], torch.from_numpy(bad).cuda(), csc[2]))
+    assert ei.value.status == capi.ALS_E_INDEX
+    a.close()
+    b.close()
+
+
+def Uo_of(ora, p):
+    Uo, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, p.M0.astype(np.float64), p.lam, p.budget_num,
+                           p.budget_den, p.min_keep)
+    return Uo
+
+
+@gpu
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_max_rel_residual_reported(ora, prec):
+    """BF16 modes report the largest relative residual |b - A u0| / |b| of a
+    refined row's first solution: about kappa 2^-9 on these well-conditioned
+    rows; FP32 refines nothing and reports 0."""
+    import torch
+    name, p = heavy_cases()[0]
+    als = make_als(p, precision=prec, **HEAVY_KW)
+    _, st = als.half_sweep_users(torch.from_numpy(p.M0).cuda(), stats=True)
+    note(f"[max residual prec={prec}] {st.max_rel_residual:.2e}")
+    if prec == 0:
+        assert st.max_rel_residual == 0.0
+    else:
+        assert 0.0 < st.max_rel_residual < 1e-1
+    als.close()
