@@ -72,6 +72,18 @@ typedef enum {
                              half_sweep_items, core_select(side 1) and objective
                              return ALS_E_STATE (contexts of new users to fold
                              in, see foldin_answer) */
+#define ALS_FAST_VARIANT 8u /* the fast variant of Core-ALS (Section 3, the
+                               paragraph after Algorithm 2): before each
+                               half-sweep CES is applied once to the whole
+                               factor matrix of the other side (rate r, budget
+                               floor(n_other r) per column), and every row
+                               regresses on that global sketch: A = X*^T X +
+                               lambda n_i E with X* the row's rows of the
+                               sketch, a singular A replaced by eq. (U).  The
+                               number of kept entries per row then only follows
+                               r on average.  Needs n_f <= 64, ALS_PREC_FP32,
+                               both sides (not ALS_USERS_ONLY); core_select is
+                               replaced by core_select_global */
 #define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
                                  even where 32-bit buffer offsets would do (the
                                  path taken for factor matrices of 2^24 rows or
@@ -192,6 +204,15 @@ als_status core_select_count(als_ctx *c, int side, int64_t row_begin, int64_t ro
  * core_select_count.  Asynchronous. */
 als_status core_select(als_ctx *c, int side, const float *other, int64_t row_begin,
                        int64_t row_end, int64_t *sel_ptr, int32_t *sel_pos, int64_t sel_cap);
+
+/* The fast variant's global sketch (ALS_FAST_VARIANT contexts): CES of
+ * Algorithm 1 on the whole matrix `other` (M for side 0, U for side 1; n_other
+ * x n_f) with budget s = min(n_other, max(min_keep, floor(n_other r))) per
+ * column.  Writes the cut of column a: T[a], K[a] (device int32 [n_f]); entry
+ * (j, a) is kept iff bits(|other[j][a]|) > T[a], or equal and j <= K[a]
+ * (ties keep the smaller row j).  Asynchronous.  ALS_E_STATE on contexts
+ * without ALS_FAST_VARIANT. */
+als_status core_select_global(als_ctx *c, int side, const float *other, int32_t *T, int32_t *K);
 
 /* Objective of Section 2.1 at (U, M), with SSE, RMSE and ReMSE (Section 5.1),
  * accumulated in FP64 in a fixed order (deterministic).  out is (host).  Syncs. */

@@ -36,7 +36,7 @@ class CoreALS:
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
                  light_blocks: int = 0, graphs: bool = False, users_only: bool = False,
-                 generic_gathers: bool = False, csc=None):
+                 generic_gathers: bool = False, csc=None, fast: bool = False):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -54,7 +54,8 @@ class CoreALS:
         p.min_keep = int(min_keep)
         p.precision = int(precision)
         p.flags = ((capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
-                   | (capi.ALS_GENERIC_GATHERS if generic_gathers else 0))
+                   | (capi.ALS_GENERIC_GATHERS if generic_gathers else 0)
+                   | (capi.ALS_FAST_VARIANT if fast else 0))
         p.stream = self.stream.cuda_stream
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)
@@ -111,6 +112,15 @@ class CoreALS:
         capi.core_select(self.ctx, side, other.data_ptr(), row_begin, row_end, sel_ptr.data_ptr(),
                          sel_pos.data_ptr(), cnt)
         return sel_ptr, sel_pos[:cnt]
+
+    def core_select_global(self, side: int, other: torch.Tensor):
+        """Fast variant: the global cut (T, K) of `other`, int32 [n_f] each."""
+        n_other = self.n_m if side == 0 else self.n_u
+        _need(other, torch.float32, n_other * self.n_f, "other")
+        T = torch.empty(self.n_f, dtype=torch.int32, device=self.device)
+        K = torch.empty(self.n_f, dtype=torch.int32, device=self.device)
+        capi.core_select_global(self.ctx, side, other.data_ptr(), T.data_ptr(), K.data_ptr())
+        return T, K
 
     def objective(self, U: torch.Tensor, M: torch.Tensor) -> dict:
         _need(U, torch.float32, self.n_u * self.n_f, "U")

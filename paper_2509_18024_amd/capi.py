@@ -18,6 +18,7 @@ ALS_PREC_FP32, ALS_PREC_BF16_IR, ALS_PREC_BF16_IR_FP64RES, ALS_PREC_AUTO = 0, 1,
 ALS_VALIDATE = 1
 ALS_USERS_ONLY = 2
 ALS_GENERIC_GATHERS = 4
+ALS_FAST_VARIANT = 8
 FOLDIN_BF16, FOLDIN_FP32 = 0, 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
@@ -80,7 +81,8 @@ EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_ite
            "foldin_param_count", "foldin_workspace_size", "foldin_create", "foldin_get_params",
            "foldin_set_params", "foldin_forward", "foldin_grad", "foldin_adamw", "foldin_train",
            "foldin_answer", "foldin_destroy", "foldin_last_error",
-           "half_sweep_noalloc", "half_sweep_noalloc_scratch_bytes", "half_sweep_noalloc_pair_cap"]
+           "half_sweep_noalloc", "half_sweep_noalloc_scratch_bytes", "half_sweep_noalloc_pair_cap",
+           "core_select_global"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
 NPROF = 12
@@ -112,6 +114,8 @@ def load():
     L.half_sweep_noalloc_scratch_bytes.argtypes = []
     L.half_sweep_noalloc_pair_cap.restype = i64
     L.half_sweep_noalloc_pair_cap.argtypes = []
+    L.core_select_global.restype = i32
+    L.core_select_global.argtypes = [vp, i32, vp, vp, vp]
     L.core_select_count.restype = i32
     L.core_select_count.argtypes = [vp, i32, i64, i64, ctypes.POINTER(ctypes.c_int64)]
     L.core_select.restype = i32
@@ -209,6 +213,10 @@ def core_select(ctx, side: int, other_ptr: int, row_begin: int, row_end: int, se
                 sel_pos_ptr: int, sel_cap: int) -> None:
     _check(load().core_select(ctx, side, other_ptr, row_begin, row_end, sel_ptr_ptr, sel_pos_ptr,
                               sel_cap), ctx)
+
+
+def core_select_global(ctx, side: int, other_ptr: int, T_ptr: int, K_ptr: int) -> None:
+    _check(load().core_select_global(ctx, side, other_ptr, T_ptr, K_ptr), ctx)
 
 
 def objective(ctx, U_ptr: int, M_ptr: int) -> als_objective:

@@ -46,6 +46,8 @@ struct Layout {
     float *partials;
     double *resid;
     uint16_t *key16;
+    void *gsel;            // fast variant: radix-select state
+    int32_t *gT, *gK;      // fast variant: the global cut [64]
     struct SideArrays {
         int32_t *pair_slot, *pair_chunk, *cutT, *cutK, *flag;
         int64_t *pair_off;
@@ -115,7 +117,11 @@ Layout carve(const als_problem &p, void *base) {
     // core-elements runs: top 16 bits of each |x| of the fixed factor
     // matrix, read by the first two selection passes
     const int64_t other_max = uo ? p.n_m : std::max(p.n_u, p.n_m);
-    L.key16 = c.take<uint16_t>(p.budget_num < p.budget_den ? (size_t)other_max * p.n_f : 0);
+    const bool fast = (p.flags & ALS_FAST_VARIANT) != 0;
+    L.key16 = c.take<uint16_t>(p.budget_num < p.budget_den && !fast ? (size_t)other_max * p.n_f : 0);
+    L.gsel = c.take<char>(fast ? global_select_state_bytes() : 0);
+    L.gT = c.take<int32_t>(64);
+    L.gK = c.take<int32_t>(64);
     for (int sd = 0; sd < 2; ++sd) {
         const int64_t nr = sd == 0 ? p.n_u : (uo ? 0 : p.n_m);
         const int64_t hb = heavy_bound(p, nr), pb = nr ? pair_bound(p, nr) : 0;
@@ -188,7 +194,36 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         c->marks.push_back(mk);
         return e;
     };
-    for (int cls = 0; cls < CLS_HEAVY; ++cls) {
+    if (c->fast) {
+        if (chk) return fail(c, ALS_E_STATE, "fold-in answers need the per-row method%s");
+        // the global sketch of `other`, then every light row in one launch
+        als_ctx::Mark mg{}, ml{};
+        HIP_CHECK(c, mark_begin(PROF_HSELECT, mg));
+        HIP_CHECK(c, launch_global_select(other, S.n_other, c->p.n_f, c->p.budget_num, c->p.budget_den,
+                                          c->p.min_keep, c->gsel, c->gT, c->gK, c->stream));
+        HIP_CHECK(c, mark_end(mg));
+        SweepArgs a{};
+        a.ptr = S.ptr;
+        a.idx = S.idx;
+        a.val = S.val;
+        a.other = other;
+        a.out = out;
+        a.perm = S.perm;
+        a.count = S.class_off[CLS_HEAVY];
+        a.nf = c->p.n_f;
+        a.lam = (float)c->p.lambda;
+        a.num = c->p.budget_num;
+        a.den = c->p.budget_den;
+        a.min_keep = c->p.min_keep;
+        a.stats = sc.stats;
+        a.queue = queues;
+        a.gT = c->gT;
+        a.gK = c->gK;
+        HIP_CHECK(c, mark_begin(CLS_FULL, ml));
+        HIP_CHECK(c, launch_sweep_fast(a, c->light_blocks, c->stream));
+        HIP_CHECK(c, mark_end(ml));
+    }
+    for (int cls = 0; cls < CLS_HEAVY && !c->fast; ++cls) {
         SweepArgs a{};
         a.ptr = S.ptr;
         a.idx = S.idx;
@@ -244,6 +279,14 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.col_base = 0;
         h.flag = c->flag[side];
         h.pass = 0;
+        h.gpos = 0;
+        if (c->fast) {
+            // one cut per column for every heavy row, ties by row index
+            h.gpos = 1;
+            h.cstride = 0;
+            h.cutT = c->gT;
+            h.cutK = c->gK;
+        }
         h.partials = sc.partials;
         h.resid = sc.resid;
         h.refine = 0;
@@ -255,7 +298,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.tol = 0.f;
         h.path = nullptr;
         h.rho = nullptr;
-        if (c->p.budget_num < c->p.budget_den) {
+        if (c->p.budget_num < c->p.budget_den && !c->fast) {
             if (c->key16 && h.other_rows > 0 && h.other_rows * h.nf * 4 <= (int64_t)0x7FFFFFFF) {
                 // (the selection reads the copy only where it gathers by buffer loads)
                 HIP_CHECK(c, launch_key16(other, h.other_rows * h.nf, c->key16, c->stream));
@@ -447,6 +490,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (p->budget_den == 0 || p->budget_num == 0 || p->budget_num > p->budget_den)
         return fail(nullptr, ALS_E_ARG, "budget rate must satisfy 0 < num <= den%s");
     if (p->min_keep < 0) return fail(nullptr, ALS_E_ARG, "min_keep must be >= 0%s");
+    if ((p->flags & ALS_FAST_VARIANT) &&
+        (p->n_f > NF || p->precision != ALS_PREC_FP32 || (p->flags & ALS_USERS_ONLY)))
+        return fail(nullptr, ALS_E_ARG, "the fast variant needs n_f <= 64, FP32 and both sides%s");
     if (p->precision < ALS_PREC_FP32 || p->precision > ALS_PREC_AUTO)
         return fail(nullptr, ALS_E_ARG, "unknown precision mode%s");
     if (!p->row_ptr || (p->nnz > 0 && (!p->col_idx || !p->val)))
@@ -473,7 +519,11 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->obj_out = L.obj_out;
     c->partials = L.partials;
     c->resid = L.resid;
-    c->key16 = p->budget_num < p->budget_den ? L.key16 : nullptr;
+    c->fast = (p->flags & ALS_FAST_VARIANT) != 0;
+    c->key16 = p->budget_num < p->budget_den && !c->fast ? L.key16 : nullptr;
+    c->gsel = L.gsel;
+    c->gT = L.gT;
+    c->gK = L.gK;
     c->bf16 = p->precision != ALS_PREC_FP32;
     // FP64 residual: always (FP64RES), per row (AUTO: lambda < 1e-3 and a
     // large pivot ratio), or never
@@ -701,6 +751,19 @@ als_status core_select(als_ctx *c, int side, const float *other, int64_t row_beg
         if (c->wide) HIP_CHECK(c, launch_select_wide(a, c->stream));
         else HIP_CHECK(c, launch_select(a, c->stream));
     }
+    return ALS_OK;
+}
+
+als_status core_select_global(als_ctx *c, int side, const float *other, int32_t *T, int32_t *K) {
+    if (!c) return ALS_E_STATE;
+    if (side != 0 && side != 1) return fail(c, ALS_E_ARG, "side must be 0 or 1%s");
+    if (side == 1 && c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
+    if (!c->fast) return fail(c, ALS_E_STATE, "context was created without ALS_FAST_VARIANT%s");
+    if (!other || !T || !K) return fail(c, ALS_E_ARG, "NULL pointer%s");
+    HIP_CHECK(c, launch_global_select(other, c->side[side].n_other, c->p.n_f, c->p.budget_num, c->p.budget_den,
+                                      c->p.min_keep, c->gsel, c->gT, c->gK, c->stream));
+    HIP_CHECK(c, hipMemcpyAsync(T, c->gT, sizeof(int32_t) * c->p.n_f, hipMemcpyDeviceToDevice, c->stream));
+    HIP_CHECK(c, hipMemcpyAsync(K, c->gK, sizeof(int32_t) * c->p.n_f, hipMemcpyDeviceToDevice, c->stream));
     return ALS_OK;
 }
 

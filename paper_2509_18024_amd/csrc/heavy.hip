@@ -490,6 +490,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         const float lamn = (float)((double)a.lam * (double)n);
         // the first pair's partial slot holds the kept LU factors between the
         // two solves (its partial system has been summed by then)
+        // (fast variant: every row's sketch is a core system)
         float *fac = a.partials + (a.pair_off[slot] - pair_base) * (int64_t)(NF + 1) * 64;
         float A[NF];
         float rhs = 0.f;
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         }
         finish_system(A, rhs, lamn, lane, a.nf);
         float u = 0.f;
-        const bool core = s < n;
+        const bool core = a.gpos || s < n;
         bool ok;
         if (a.keep) {
             // a refinement step follows: keep the factors for it
@@ -723,7 +724,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, v);
 }
 
-template <bool BUF>
+// GPOS (fast variant): one cut per column for every row (cstride 0), its tie
+// rule applied to the entry's row index in `other` instead of its position.
+template <bool BUF, bool GPOS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_x6(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
@@ -752,13 +755,14 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
         // kept(k) <=> (key, ~k) >= (T, ~K) as unsigned 64-bit pairs; every
         // entry is kept with (T, K) = (0, INT_MAX), none with s = 0
         int T0 = 0, K0 = 0x7FFFFFFF, T1 = 0, K1 = 0x7FFFFFFF;
-        if (s < n) {
-            T0 = a.cutT[slot * 64 + m];
-            K0 = a.cutK[slot * 64 + m];
-            T1 = a.cutT[slot * 64 + 32 + m];
-            K1 = a.cutK[slot * 64 + 32 + m];
+        if (GPOS || s < n) {
+            const int64_t cb = slot * (int64_t)a.cstride;
+            T0 = a.cutT[cb + m];
+            K0 = a.cutK[cb + m];
+            T1 = a.cutT[cb + 32 + m];
+            K1 = a.cutK[cb + 32 + m];
         }
-        if (s == 0) {
+        if (!GPOS && s == 0) {
             T0 = T1 = 0x7FFFFFFF;
             K0 = K1 = -1;
         }
@@ -792,11 +796,13 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
             for (int e0 = k0; e0 < min(ke, k1); e0 += 16 * GX_STEPS) {
                 const int j0 = e0 - k0;
                 float x0[GX_STEPS][8], x1[GX_STEPS][8];
+                int cols[GX_STEPS][8];
 #pragma unroll
                 for (int st = 0; st < GX_STEPS; ++st)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int col = s_col[w][j0 + 16 * st + 8 * h + e];
+                        cols[st][e] = col;
                         if constexpr (BUF) {
                             const uint32_t off = __umul24((unsigned)col, (unsigned)stride);
                             x0[st][e] =
@@ -829,7 +835,8 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                                 const float x = t ? x1[st][e] : x0[st][e];
                                 xv[o] = x;
                                 const uint32_t u = __float_as_uint(x);
-                                const uint64_t key = ((uint64_t)(u & 0x7FFFFFFFu) << 32) | (nkb - (uint32_t)e);
+                                const uint32_t tie = GPOS ? ~(uint32_t)cols[st][e] : nkb - (uint32_t)e;
+                                const uint64_t key = ((uint64_t)(u & 0x7FFFFFFFu) << 32) | tie;
                                 const bool kp = key >= bt;
                                 km[o] = kp ? 0xFFFFu : 0u;
                                 const float y = s_y[w][j0 + 16 * st + 8 * h + e];
@@ -1131,8 +1138,14 @@ hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pai
     const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
                      a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
     const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
-    if (buf) hipLaunchKernelGGL(k_heavy_gram_x6<true>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
-    else hipLaunchKernelGGL(k_heavy_gram_x6<false>, grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    if (buf && a.gpos)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else if (buf)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else if (a.gpos)
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
     return hipGetLastError();
 }
 

@@ -155,6 +155,10 @@ struct SweepArgs {
     float tol;
     int32_t *path;
     float *rho;
+    // fast variant: the global cut of `other` (column a keeps key > gT[a], or
+    // key == gT[a] and row index <= gK[a]) replaces each row's selection
+    const int32_t *gT;
+    const int32_t *gK;
 };
 
 struct HeavyArgs {
@@ -187,6 +191,8 @@ struct HeavyArgs {
     int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // Fp64Mode of the refinement residual
     int32_t *flag;            // per heavy slot: 0, or the pass that redoes the row
+    int32_t gpos;             // fast variant: one cut per column (cstride 0), ties
+                              // decided by the row index of `other`, not the position
     int32_t pass;             // 0: all rows; 1 (wide ranks): rows with a singular core
                               // system, from the full data; 2 (ALS_PREC_AUTO): rows
                               // whose Gram is built again with FP32 products
@@ -249,6 +255,13 @@ hipError_t launch_wide_solve(const HeavyArgs &a, int64_t slot_begin, int64_t slo
 hipError_t launch_wide_resid(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s);
 hipError_t launch_select_wide(const SelectArgs &a, hipStream_t s);
 
+// launchers (fast.hip): the global cut of the fast variant, T / K device [64]
+size_t global_select_state_bytes();
+hipError_t launch_global_select(const float *other, int64_t n_other, int nf, uint32_t num, uint32_t den,
+                                int32_t min_keep, void *state, int32_t *T, int32_t *K, hipStream_t s);
+// light rows of the fast variant (sweep.hip): every class, one kernel
+hipError_t launch_sweep_fast(const SweepArgs &a, int max_blocks, hipStream_t s);
+
 // launchers (setup.hip)
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
@@ -295,6 +308,9 @@ struct als_ctx {
     bool bf16 = false;     // heavy-row Gram on bf16 MFMA + one refinement step
     int fp64res = 0;       // Fp64Mode of the refinement residual
     bool wide = false;     // 64 < n_f <= NFW: wide-rank kernels for every row
+    bool fast = false;     // ALS_FAST_VARIANT: one global sketch per half-sweep
+    void *gsel = nullptr;  // fast variant: radix-select state and the cut
+    int32_t *gT = nullptr, *gK = nullptr;
     int32_t *flag[2] = {nullptr, nullptr};  // per heavy slot: the pass that redoes the row
     void *temp = nullptr;
     size_t temp_bytes = 0;

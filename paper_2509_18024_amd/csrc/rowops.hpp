@@ -44,15 +44,27 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 // One wavefront's LDS: ROWS staged design rows (a chunk), their ratings and
 // the solve's scratch.  The classes of short rows stage 32-row chunks, which
 // halves the LDS per wavefront.
-template <int ROWS>
+// COLS (fast variant): the staged rows' indices into `other` are kept too,
+// and ties of the cut are decided by them instead of the positions.
+template <int ROWS, bool COLS = false>
 struct alignas(16) WaveLdsT {
     static constexpr int rows = ROWS;
+    static constexpr bool has_cols = COLS;
     float X[ROWS][NF + 4];    // staged design rows (select, Gram)
     float y[ROWS];
     float urhs[2 * NF];       // solve: solution components parked by the back substitution
     double rres[ROWS];        // refinement: residuals y_k - x_k . u of the staged rows
+    int col[COLS ? ROWS : 1]; // indices of the staged rows into `other`
 };
 using WaveLds = WaveLdsT<CK>;
+
+// The value a cut's tie rule compares for staged row k of the chunk at k0:
+// its position in the row, or (fast variant) its row index in `other`.
+template <class LDS>
+__device__ __forceinline__ int tie_pos(const LDS &L, int k0, int k) {
+    if constexpr (LDS::has_cols) return L.col[k];
+    else return k0 + k;
+}
 
 // Largest value over the wave of a non-negative-or-(-1) integer key: DPP
 // within each row of 16 lanes (xor 1, xor 2, half-row and row mirrors), then
@@ -91,6 +103,8 @@ __device__ __forceinline__ void stage_loaded(LDS &L, RowCtx &r, int k0, int col,
     wave_sync();
     const int cnt = min(LDS::rows, r.n - k0);
     if (lane < LDS::rows) L.y[lane] = yv;
+    if constexpr (LDS::has_cols)
+        if (lane < LDS::rows) L.col[lane] = col;
     // Gathers are unconditional (positions past cnt read factor row 0, which
     // exists) so the whole chunk's loads are in flight together; the padding
     // is zeroed afterwards.
@@ -321,7 +335,7 @@ __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &
         const int m = min(LDS::rows, ke - k0);
         uint64_t bits = 0;
         for (int k = 0; k < m; ++k)
-            if (kept(c, key_of(L.X[k][lane]), k0 + k)) bits |= 1ull << k;
+            if (kept(c, key_of(L.X[k][lane]), tie_pos(L, k0, k))) bits |= 1ull << k;
         while (__ballot(bits != 0ull)) {
             if (bits != 0ull) {
                 const int k = __ffsll((unsigned long long)bits) - 1;
@@ -696,7 +710,7 @@ __device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, i
 #pragma unroll
     for (int k = 0; k < WB_D; ++k) {
         const float x = L.X[k][lane];
-        keep[k] = k < n && kept(c, key_of(x), k);
+        keep[k] = k < n && kept(c, key_of(x), tie_pos(L, 0, k));
         if (keep[k]) b = fmaf(x, L.y[k], b);
     }
     if (lane >= nf) b = 0.f;

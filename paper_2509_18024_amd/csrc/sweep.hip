@@ -43,16 +43,20 @@ __device__ __forceinline__ Cut select_for_class(LDS &L, RowCtx &r, int s, int la
 // is at most a.tol; otherwise the row is solved exactly as in the sweep.
 // STRIDED: rows dealt out by wave index with the next rows' indices
 // prefetched (the grid must be resident at once); else an atomic row queue.
-template <int CLS, bool CHECK, bool STRIDED>
+// FAST (fast variant): no per-row selection; every row, of any class, keeps
+// the entries its column's global cut (a.gT, a.gK) keeps, ties decided by
+// the row index in `other`.
+template <int CLS, bool CHECK, bool STRIDED, bool FAST = false>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     // the two smallest classes solve in Woodbury form from one chunk of at
     // most WB_D rows: 32-row chunks, half the LDS per wavefront
-    using LDS = WaveLdsT<(!CHECK && (CLS == CLS_NET1 || CLS == CLS_NET2)) ? WB_D : CK>;
+    using LDS = WaveLdsT<(!CHECK && !FAST && (CLS == CLS_NET1 || CLS == CLS_NET2)) ? WB_D : CK, FAST>;
     __shared__ LDS lds[WPB];
     const int w = wave_index();
     const int lane0 = threadIdx.x & 63;
     LDS &L = lds[w];
     const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
+    const int gT = FAST ? a.gT[lane0] : 0, gK = FAST ? a.gK[lane0] : 0;
 
     // One row: i its index, [beg, beg + n) its entries; if STRIDED, col0 / y0
     // hold the column indices and ratings of its first LDS chunk (lane j:
@@ -74,7 +78,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
         }
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
         const float lamn = (float)((double)a.lam * (double)n);
-        constexpr bool kCore = CLS != CLS_FULL;
+        constexpr bool kCore = FAST || CLS != CLS_FULL;
         float g = 0.f;
         if constexpr (CHECK) {
             g = lane < a.nf ? a.guess[i * a.nf + lane] : 0.f;
@@ -83,7 +87,9 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
             wave_sync();
         }
         Cut c{0, 0, false, true};
-        if constexpr (kCore) {
+        if constexpr (FAST) {
+            c = Cut{gT, gK, false, false};
+        } else if constexpr (kCore) {
             if (s == 0) c = Cut{0, 0, true, false};
             else c = select_for_class<CLS>(L, r, s, lane);
         }
@@ -103,9 +109,9 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                 return;
             }
         }
-        if constexpr (!CHECK && (CLS == CLS_NET1 || CLS == CLS_NET2)) {
+        if constexpr (!CHECK && (FAST || CLS == CLS_NET1 || CLS == CLS_NET2)) {
             // few entries: the n x n Woodbury form of the same system
-            if (n <= WB_D && s > 0 && a.lam > 0.f) {
+            if (n <= WB_D && (FAST || s > 0) && a.lam > 0.f) {
                 stage(L, r, 0, lane);  // the whole row is chunk 0 (staged above)
                 bool masked;
                 float uw;
@@ -231,6 +237,12 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAV
     sweep_rows<CLS, false, false>(a);
 }
 
+// Light rows of the fast variant, every class in one launch (the schedule's
+// light rows are contiguous in the row order).
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_fast(SweepArgs a) {
+    sweep_rows<CLS_NET1, false, false, true>(a);
+}
+
 // Fold-in answers: residual check of the candidates, exact solve of the rest.
 __global__ __launch_bounds__(WPB * 64) void k_check_full(SweepArgs a) { sweep_rows<CLS_FULL, true, false>(a); }
 
@@ -347,6 +359,16 @@ hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipSt
 hipError_t launch_check_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
     if (!a.guess || !a.path || !a.rho) return hipErrorInvalidValue;
     return launch_class<true>(cls, a, max_blocks, s);
+}
+
+hipError_t launch_sweep_fast(const SweepArgs &a, int max_blocks, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    if (!a.gT || !a.gK) return hipErrorInvalidValue;
+    int64_t blocks = (a.count + WPB - 1) / WPB;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(k_sweep_fast, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t s) {
