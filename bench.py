@@ -3,8 +3,10 @@
 One step = one Core-ALS iteration of Algorithm 2 (users half-sweep from M,
 then items half-sweep from the new U) over the whole synthetic matrix, inputs
 already resident in HBM.  The headline line times core-elements ALS at
-r = 1/10; the same run also times r = 1/20, r = 1/4 and plain full-data ALS
-(r = 1) on the same GPU and reports their sweep times, solves/s and RMSE.
+r = 1/10; the same run also times r = 1/20, r = 1/4, the BF16 + refinement
+modes, the fast variant (one global sketch per half-sweep) and plain
+full-data ALS (r = 1) on the same GPU and reports their sweep times,
+solves/s and RMSE.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -23,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ALS sweep s & solves/s (nnz=1e8,n_f=64): core vs full ALS, RMSE gap"
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32 instructions (the library is built
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -85,7 +89,7 @@ def class_work(deg, num, den, min_keep, nf, heavy_n=1024):
     return out
 
 
-def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, precision=0, cfg=None):
+def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, precision=0, cfg=None, fast=False):
     """Time `steps` sweeps (users + items half-sweep) after `warmup` untimed
     ones, on the context's own stream: once as eager launches with per-kernel
     HIP events (the timed region), once as HIP-graph replays."""
@@ -96,7 +100,7 @@ def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, preci
     t0 = time.time()
     with torch.cuda.stream(stream):
         als = CoreALS(prob.n_u, prob.n_m, prob.n_f, rp, ci, v, prob.lam, budget, prob.min_keep, precision,
-                      stream=stream, graphs=True, **cfg)
+                      stream=stream, graphs=True, fast=fast, **cfg)
         stream.synchronize()
         init_s = time.time() - t0
         counts = capi.als_class_counts(als.ctx)
@@ -136,6 +140,7 @@ def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, preci
     res = {
         "budget": f"{budget[0]}/{budget[1]}",
         "precision": ["fp32", "bf16+ir(fp32 residual)", "bf16+ir(fp64 residual)", "auto"][precision],
+        "method": "fast variant (global sketch)" if fast else "per-row CES",
         "schedule": cfg,
         "sweep_ms": ms,
         "sweep_s": ms / 1000.0,
@@ -394,15 +399,16 @@ def main():
     prob = synth.c3_batched(scale=args.scale)
     log(f"generated n_u={prob.n_u} n_m={prob.n_m} nnz={prob.nnz} in {time.time() - t:.1f}s")
 
-    # headline: core-elements ALS, r = 1/10, FP32 throughout (heavy-row Gram on
-    # FP32 MFMA tiles); comparator: plain full-data ALS in FP32 on the same GPU
+    # headline: core-elements ALS, r = 1/10, FP32 throughout (heavy-row Gram:
+    # FP32 products on bf16 MFMA tiles); comparator: plain full-data ALS in FP32 on the same GPU
     from paper_2509_18024_amd import autotune
     HEAD = "core_r1/10_fp32"
-    variants = [(HEAD, (1, 10), 0)]
+    variants = [(HEAD, (1, 10), 0, False)]
     if not args.headline_only:
-        variants += [("core_r1/10_bf16ir", (1, 10), 1), ("core_r1/20_fp32", (1, 20), 0),
-                     ("core_r1/4_fp32", (1, 4), 0), ("full_fp32", (1, 1), 0),
-                     ("full_bf16ir", (1, 1), 1)]
+        variants += [("core_r1/10_bf16ir", (1, 10), 1, False), ("core_r1/10_auto", (1, 10), 3, False),
+                     ("core_fast_r1/10_fp32", (1, 10), 0, True),
+                     ("core_r1/20_fp32", (1, 20), 0, False), ("core_r1/4_fp32", (1, 4), 0, False),
+                     ("full_fp32", (1, 1), 0, False), ("full_bf16ir", (1, 1), 1, False)]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         gpu_csr = (torch.from_numpy(prob.row_ptr).to(dev), torch.from_numpy(prob.col_idx).to(dev),
@@ -428,9 +434,10 @@ def main():
             schedules[key] = autotune.tune(torch, prob, gpu_csr, b, prec, stream, log, path=tune_out)
     results = {}
     head_als = None
-    for tag, b, prec in variants:
+    for tag, b, prec, fast in variants:
         cfg = schedules["full" if b[0] == b[1] else "core"]
-        als, res, M_fin = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg)
+        als, res, M_fin = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg,
+                                       fast)
         results[tag] = res
         if tag == HEAD:
             head_als = als
@@ -470,7 +477,7 @@ def main():
                 "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "kernel": kname, "group": capi.PROF_NAMES[c], "avg_launch_ms": avg_ms, "launches_per_sweep": lps,
                 "algorithmic_bytes_per_launch": w_bytes / lps, "algorithmic_flops_per_launch": w_flops / lps,
-                "fp32_tflops": tfl, "fp32_frac_of_157": tfl / FP32_VALU_PEAK_TFLOPS}
+                "fp32_tflops": tfl, "fp32_frac_of_78_6": tfl / FP32_VALU_PEAK_TFLOPS}
     per_kernel = {}
     for s_, c_ in groups:
         n_l = head["kernel_launches"][s_][c_]
@@ -520,15 +527,15 @@ def main():
             "workload": (f"c3_batched: n_u={prob.n_u}, n_m={prob.n_m}, n_f={prob.n_f}, "
                          f"nnz={prob.nnz}, user degree 1+Lomax(1.5) capped 50k, item popularity "
                          f"Zipf(1.1) water-filled at 50k, lambda={prob.lam}, core-elements r=1/10, "
-                         f"FP32 throughout (heavy-row Gram on FP32 MFMA tiles); "
-                         f"step = users + items half-sweep"),
+                         f"FP32 throughout (heavy-row Gram: FP32 products from an exact three-way bf16 "
+                         f"split on bf16 MFMA tiles); step = users + items half-sweep"),
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep_s": head["sweep_s"],
-        "core_vs_full": {k: {kk: v[kk] for kk in ("budget", "precision", "sweep_s", "solves_per_s", "rmse",
-                                                   "iterations_done")}
+        "core_vs_full": {k: {kk: v[kk] for kk in ("budget", "precision", "method", "sweep_s", "solves_per_s",
+                                                   "rmse", "iterations_done")}
                          for k, v in results.items()},
         "method_rmse_gap_vs_full": ({k: v["rmse"] - full["rmse"] for k, v in results.items()}
                                     if full else None),
