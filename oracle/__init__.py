@@ -74,6 +74,18 @@ def lib():
         L.ora_fast_half_sweep.argtypes = [ctypes.c_int64, ctypes.c_int32, I64P, I32P, F32P, ctypes.c_int64,
                                           F64P, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int64, F64P, I64P]
+        L.ora_splitmix64.restype = ctypes.c_uint64
+        L.ora_splitmix64.argtypes = [ctypes.c_uint64]
+        L.ora_unif_key.restype = ctypes.c_uint32
+        L.ora_unif_key.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.ora_unif_select.argtypes = [ctypes.c_int64, I32P, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                      ctypes.c_int64, U8P]
+        L.ora_unif_row.restype = ctypes.c_int
+        L.ora_unif_row.argtypes = [ctypes.c_int64, ctypes.c_int32, F64P, U8P, F64P, ctypes.c_double,
+                                   ctypes.c_int64, F64P]
+        L.ora_unif_half_sweep.argtypes = [ctypes.c_int64, ctypes.c_int32, I64P, I32P, F32P, ctypes.c_int64,
+                                          F64P, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_uint64, F64P, I64P]
         _lib = L
     return _lib
 
@@ -216,6 +228,47 @@ def fast_half_sweep(row_ptr, col_idx, val, other, lam, num, den, min_keep):
     st = np.zeros(2, np.int64)
     lib().ora_fast_half_sweep(n_rows, nf, _p(rp, I64P), _p(ci, I32P), _p(v, F32P), O.shape[0], _p(O, F64P),
                               float(lam), int(num), int(den), int(min_keep), _p(out, F64P), _p(st, I64P))
+    return out, st
+
+
+def splitmix64(x: int) -> int:
+    """splitmix64 (Steele, Lea and Flood, 2014): the output for state x."""
+    return int(lib().ora_splitmix64(ctypes.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+def unif_select(cols, row, n_cols, seed, s):
+    """UNIF draw of one row (Section 5 comparator): the s entries with the
+    smallest keys h(seed, row, col).  Returns the kept mask (uint8 [n])."""
+    c = _c(cols, np.int32)
+    keep = np.zeros(len(c), np.uint8)
+    lib().ora_unif_select(len(c), _p(c, I32P), int(row), int(n_cols), ctypes.c_uint64(seed), int(s),
+                          keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return keep
+
+
+def unif_row(X, keep, y, lam, s):
+    """Ridge regression of a UNIF subsample: (X_S^T X_S + lambda s E) u = X_S^T y_S."""
+    X = _c(X, np.float64)
+    keep = _c(keep, np.uint8)
+    y = _c(y, np.float64)
+    n, nf = X.shape
+    u = np.zeros(nf, np.float64)
+    st = lib().ora_unif_row(n, nf, _p(X, F64P), keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            _p(y, F64P), float(lam), int(s), _p(u, F64P))
+    return u, st
+
+
+def unif_half_sweep(row_ptr, col_idx, val, other, lam, num, den, min_keep, seed):
+    """One half-sweep of UNIF (Section 5).  Returns (out, stats)."""
+    rp, ci, v = _c(row_ptr, np.int64), _c(col_idx, np.int32), _c(val, np.float32)
+    O = _c(other, np.float64)
+    n_rows = len(rp) - 1
+    nf = O.shape[1]
+    out = np.zeros((n_rows, nf), np.float64)
+    st = np.zeros(2, np.int64)
+    lib().ora_unif_half_sweep(n_rows, nf, _p(rp, I64P), _p(ci, I32P), _p(v, F32P), O.shape[0], _p(O, F64P),
+                              float(lam), int(num), int(den), int(min_keep), ctypes.c_uint64(seed),
+                              _p(out, F64P), _p(st, I64P))
     return out, st
 
 

@@ -17,6 +17,7 @@
  *  - the core estimator u = (X*^T X + lambda n_i E)^-1 X*^T y
  *                                                          (Section 3, eq. core_ui/core_mj)
  *  - one half-sweep of Core-ALS over all rows              (Section 3, Algorithm 2)
+ *  - UNIF, the uniform-subsampling comparator           (Section 5, Tables 1, 2)
  *  - the fast variant: CES once per half-sweep on the whole factor matrix of
  *    the other side, each row regressing on that global sketch
  *                                                          (Section 3, the paragraph
@@ -499,5 +500,114 @@ void ora_fast_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr, con
     if (stats) {
         stats[0] = n_empty;
         stats[1] = n_fallback;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * UNIF, the uniform-subsampling comparator of Section 5 (Table 1 and 2).
+ * Reading (the paper names the method and its rate only): each regression
+ * draws s = budget(n) of its n observed entries uniformly without
+ * replacement and solves the ridge regression of that sample,
+ *     (X_S^T X_S + lambda s E) u = X_S^T y_S,
+ * the weighted-lambda rule of Section 2.1 applied to the subsample (the same
+ * system as the inverse-probability-weighted estimator with lambda n, scaled
+ * by s / n).  The draw: the s entries whose key h(seed, row, col) is smallest
+ * (ties: smaller position), with h the upper 32 bits of splitmix64 (Steele,
+ * Lea and Flood, 2014) at seed * 0x9E3779B97F4A7C15 + row * n_cols + col.
+ * ---------------------------------------------------------------------- */
+
+uint64_t ora_splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint32_t ora_unif_key(uint64_t seed, int64_t row, int64_t n_cols, int64_t col) {
+    return (uint32_t)(ora_splitmix64(seed * 0x9E3779B97F4A7C15ull + (uint64_t)(row * n_cols + col)) >> 32);
+}
+
+typedef struct {
+    uint32_t key;
+    int32_t pos;
+} ora_ukey;
+
+static int ora_ukey_cmp(const void *pa, const void *pb) {
+    const ora_ukey *a = (const ora_ukey *)pa, *b = (const ora_ukey *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return (a->pos > b->pos) - (a->pos < b->pos);
+}
+
+/* keep[k] = 1 for the s entries of the row with the smallest keys. */
+void ora_unif_select(int64_t n, const int32_t *cols, int64_t row, int64_t n_cols, uint64_t seed, int64_t s,
+                     uint8_t *keep) {
+    ora_ukey *k = (ora_ukey *)malloc(sizeof(ora_ukey) * (size_t)(n > 0 ? n : 1));
+    for (int64_t t = 0; t < n; ++t) {
+        k[t].key = ora_unif_key(seed, row, n_cols, cols[t]);
+        k[t].pos = (int32_t)t;
+        keep[t] = 0;
+    }
+    qsort(k, (size_t)n, sizeof(ora_ukey), ora_ukey_cmp);
+    for (int64_t t = 0; t < s && t < n; ++t) keep[k[t].pos] = 1;
+    free(k);
+}
+
+/* The subsample's ridge regression; returns 1 for an empty row, 3 when the
+ * system is singular (s = 0 at any lambda, or lambda = 0 with a rank-deficient
+ * sample): u = 0. */
+int ora_unif_row(int64_t n, int32_t nf, const double *X, const uint8_t *keep, const double *y, double lam,
+                 int64_t s, double *u) {
+    if (n == 0) {
+        for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+        return 1;
+    }
+    double *G = (double *)calloc((size_t)nf * nf, sizeof(double));
+    for (int32_t a = 0; a < nf; ++a) {
+        double acc = 0.0;
+        for (int64_t k = 0; k < n; ++k)
+            if (keep[k]) acc += X[k * nf + a] * y[k];
+        u[a] = acc;
+        for (int32_t c = 0; c < nf; ++c) {
+            double g = 0.0;
+            for (int64_t k = 0; k < n; ++k)
+                if (keep[k]) g += X[k * nf + a] * X[k * nf + c];
+            G[a * nf + c] = g;
+        }
+        G[a * nf + a] += lam * (double)s;
+    }
+    double gmax = 0.0;
+    for (int64_t e = 0; e < (int64_t)nf * nf; ++e) gmax = fmax(gmax, fabs(G[e]));
+    int bad = ora_cholesky_solve(nf, G, u, (double)nf * ldexp(1.0, -52) * gmax);
+    if (bad || gmax == 0.0)
+        for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+    free(G);
+    return (bad || gmax == 0.0) ? 3 : 0;
+}
+
+/* One half-sweep of UNIF.  stats[0] empty rows, stats[1] singular systems. */
+void ora_unif_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr, const int32_t *col_idx,
+                         const float *val, int64_t n_cols, const double *other, double lam, int64_t num,
+                         int64_t den, int64_t min_keep, uint64_t seed, double *out, int64_t *stats) {
+    int64_t n_empty = 0, n_sing = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_empty, n_sing)
+    for (int64_t i = 0; i < n_rows; ++i) {
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        uint8_t *keep = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+        ora_gather(beg, n, nf, col_idx, val, other, X, y);
+        int64_t s = ora_budget(n, num, den, min_keep);
+        ora_unif_select(n, col_idx + beg, i, n_cols, seed, s, keep);
+        int st = ora_unif_row(n, nf, X, keep, y, lam, s, out + i * nf);
+        if (st == 1) n_empty++;
+        if (st == 3) n_sing++;
+        free(X);
+        free(y);
+        free(keep);
+    }
+    if (stats) {
+        stats[0] = n_empty;
+        stats[1] = n_sing;
     }
 }

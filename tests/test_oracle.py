@@ -484,3 +484,81 @@ def test_fast_masked_row_singular_fallback(ora):
     assert np.allclose(u, np.linalg.lstsq(X, y, rcond=None)[0], rtol=1e-10)
     u1, st1 = ora.masked_row(X, np.ones((20, 3), np.uint8), y, 0.0)
     assert st1 == 0 and np.allclose(u1, np.linalg.lstsq(X, y, rcond=None)[0], rtol=1e-10)
+
+
+# ---------------------------------------------------------------- UNIF
+# (the uniform-subsampling comparator of Section 5: s = budget(n) entries drawn
+# uniformly without replacement per regression, the subsample's ridge system)
+
+def test_splitmix64_reference_vector(ora):
+    """The generator behind the UNIF draws against its published outputs."""
+    g = json.load(open(os.path.join(GOLD, "splitmix64.json")))
+    gamma = 0x9E3779B97F4A7C15
+    for k, want in enumerate(g["outputs"]):
+        assert ora.splitmix64((g["seed"] + k * gamma) % (1 << 64)) == int(want)
+
+
+def test_unif_draw_is_uniform_without_replacement(ora):
+    """Exactly s of the n entries, every entry with probability s / n: over
+    4000 seeds each inclusion frequency lies within 4 standard deviations of
+    s / n, and pairs are included together with probability s(s-1)/(n(n-1))."""
+    n, s, trials = 20, 5, 4000
+    cols = np.arange(0, 3 * n, 3, dtype=np.int32)
+    inc = np.zeros(n)
+    pair = 0
+    for seed in range(trials):
+        keep = ora.unif_select(cols, 7, 1000, seed, s)
+        assert keep.sum() == s
+        inc += keep
+        pair += keep[0] * keep[1]
+    p = s / n
+    sd = math.sqrt(p * (1 - p) / trials)
+    assert np.all(np.abs(inc / trials - p) <= 4 * sd)
+    p2 = s * (s - 1) / (n * (n - 1))
+    assert abs(pair / trials - p2) <= 4 * math.sqrt(p2 * (1 - p2) / trials)
+
+
+def test_unif_row_is_ridge_on_the_sample(ora):
+    """The UNIF system equals ridge regression on the drawn rows with weight
+    lambda s, solved through QR (lstsq of the augmented problem)."""
+    rng = np.random.default_rng(74)
+    X = rng.normal(0, 1, (40, 5))
+    y = rng.normal(0, 1, 40)
+    keep = ora.unif_select(np.arange(40, dtype=np.int32) * 2, 3, 100, 11, 12)
+    lam, s = 0.3, 12
+    u, st = ora.unif_row(X, keep, y, lam, s)
+    Xs = X[keep.astype(bool)]
+    aug = np.vstack([Xs, math.sqrt(lam * s) * np.eye(5)])
+    ref = np.linalg.lstsq(aug, np.concatenate([y[keep.astype(bool)], np.zeros(5)]), rcond=None)[0]
+    assert st == 0 and np.allclose(u, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_unif_full_budget_is_exact_als(ora):
+    p = synth.random_problem(75, 50, 40, 5, 0.3, budget=(1, 1))
+    O = p.M0.astype(np.float64)
+    unif, _ = ora.unif_half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, 1, 1, 1, 5)
+    full, _ = ora.half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, 1, 1, 1)
+    assert np.allclose(unif, full, rtol=1e-11, atol=1e-13)
+
+
+def test_unif_half_sweep_vs_dense(ora):
+    """Each row: the oracle's own draw, then LAPACK on the explicit subsample;
+    s = 0 rows (min_keep = 0) give u = 0 and count as singular."""
+    p = synth.random_problem(76, 60, 50, 6, 0.3, budget=(1, 4), min_keep=0)
+    O = p.M0.astype(np.float64)
+    out, st = ora.unif_half_sweep(p.row_ptr, p.col_idx, p.val, O, p.lam, 1, 4, 0, 9)
+    n_zero = 0
+    for i in range(p.n_u):
+        b, e = p.row_ptr[i], p.row_ptr[i + 1]
+        cols = p.col_idx[b:e]
+        s = (e - b) // 4
+        if s == 0:
+            n_zero += int(e > b)
+            assert np.all(out[i] == 0)
+            continue
+        keep = ora.unif_select(cols, i, p.n_m, 9, s).astype(bool)
+        X = O[cols][keep]
+        y = p.val[b:e][keep].astype(np.float64)
+        ref = np.linalg.solve(X.T @ X + p.lam * s * np.eye(6), X.T @ y)
+        assert np.allclose(out[i], ref, rtol=1e-10, atol=1e-12)
+    assert st[1] == n_zero
