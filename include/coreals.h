@@ -84,6 +84,18 @@ typedef enum {
                                r on average.  Needs n_f <= 64, ALS_PREC_FP32,
                                both sides (not ALS_USERS_ONLY); core_select is
                                replaced by core_select_global */
+#define ALS_UNIF 16u /* UNIF, the uniform-subsampling comparator of Section 5:
+                        each regression draws s = min(n_i, max(min_keep,
+                        floor(n_i r))) of its entries uniformly without
+                        replacement (the s smallest keys h(seed, row, col) =
+                        upper 32 bits of splitmix64 at seed * 0x9E3779B97F4A7C15
+                        + row * n_cols + col, ties by position; n_cols = rows
+                        of the other factor matrix) and solves
+                        (X_S^T X_S + lambda s E) u = X_S^T y_S.  The seed is
+                        set with als_set_sample_seed (default 0).  Needs
+                        n_f <= 64, ALS_PREC_FP32, not ALS_FAST_VARIANT;
+                        n_singular_fallback counts singular sample systems
+                        (answered with u = 0) */
 #define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
                                  even where 32-bit buffer offsets would do (the
                                  path taken for factor matrices of 2^24 rows or
@@ -229,6 +241,10 @@ als_status objective(als_ctx *c, const float *U, const float *M, als_objective *
  * solves.  Either array may be NULL.  Profiling then stops. */
 als_status als_profile_begin(als_ctx *c);
 als_status als_profile_end(als_ctx *c, double *ms, int64_t *launches);
+
+/* Seed of the UNIF draws of the following half-sweeps (ALS_UNIF contexts;
+ * no effect otherwise).  No device call. */
+als_status als_set_sample_seed(als_ctx *c, uint64_t seed);
 
 /* Capture each half-sweep into a HIP graph on its first call and replay the
  * graph on later calls with the same factor pointers (a call with other

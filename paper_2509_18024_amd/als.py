@@ -36,7 +36,7 @@ class CoreALS:
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
                  light_blocks: int = 0, graphs: bool = False, users_only: bool = False,
-                 generic_gathers: bool = False, csc=None, fast: bool = False):
+                 generic_gathers: bool = False, csc=None, fast: bool = False, unif: bool = False):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -55,7 +55,7 @@ class CoreALS:
         p.precision = int(precision)
         p.flags = ((capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
                    | (capi.ALS_GENERIC_GATHERS if generic_gathers else 0)
-                   | (capi.ALS_FAST_VARIANT if fast else 0))
+                   | (capi.ALS_FAST_VARIANT if fast else 0) | (capi.ALS_UNIF if unif else 0))
         p.stream = self.stream.cuda_stream
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)
@@ -112,6 +112,10 @@ class CoreALS:
         capi.core_select(self.ctx, side, other.data_ptr(), row_begin, row_end, sel_ptr.data_ptr(),
                          sel_pos.data_ptr(), cnt)
         return sel_ptr, sel_pos[:cnt]
+
+    def set_sample_seed(self, seed: int) -> None:
+        """UNIF: the seed of the following half-sweeps' uniform draws."""
+        capi.als_set_sample_seed(self.ctx, seed)
 
     def core_select_global(self, side: int, other: torch.Tensor):
         """Fast variant: the global cut (T, K) of `other`, int32 [n_f] each."""

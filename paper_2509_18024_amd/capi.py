@@ -19,6 +19,7 @@ ALS_VALIDATE = 1
 ALS_USERS_ONLY = 2
 ALS_GENERIC_GATHERS = 4
 ALS_FAST_VARIANT = 8
+ALS_UNIF = 16
 FOLDIN_BF16, FOLDIN_FP32 = 0, 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
@@ -82,7 +83,7 @@ EXPORTS = ["als_workspace_size", "als_init", "half_sweep_users", "half_sweep_ite
            "foldin_set_params", "foldin_forward", "foldin_grad", "foldin_adamw", "foldin_train",
            "foldin_answer", "foldin_destroy", "foldin_last_error",
            "half_sweep_noalloc", "half_sweep_noalloc_scratch_bytes", "half_sweep_noalloc_pair_cap",
-           "core_select_global"]
+           "core_select_global", "als_set_sample_seed"]
 NCLASS = 8
 CLASS_NAMES = ["full", "net1", "net2", "net4", "net8", "net16", "net32", "heavy"]
 NPROF = 12
@@ -114,6 +115,8 @@ def load():
     L.half_sweep_noalloc_scratch_bytes.argtypes = []
     L.half_sweep_noalloc_pair_cap.restype = i64
     L.half_sweep_noalloc_pair_cap.argtypes = []
+    L.als_set_sample_seed.restype = i32
+    L.als_set_sample_seed.argtypes = [vp, ctypes.c_uint64]
     L.core_select_global.restype = i32
     L.core_select_global.argtypes = [vp, i32, vp, vp, vp]
     L.core_select_count.restype = i32
@@ -213,6 +216,10 @@ def core_select(ctx, side: int, other_ptr: int, row_begin: int, row_end: int, se
                 sel_pos_ptr: int, sel_cap: int) -> None:
     _check(load().core_select(ctx, side, other_ptr, row_begin, row_end, sel_ptr_ptr, sel_pos_ptr,
                               sel_cap), ctx)
+
+
+def als_set_sample_seed(ctx, seed: int) -> None:
+    _check(load().als_set_sample_seed(ctx, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF)), ctx)
 
 
 def core_select_global(ctx, side: int, other_ptr: int, T_ptr: int, K_ptr: int) -> None:

@@ -49,6 +49,8 @@ struct Layout {
     void *gsel;            // fast variant: radix-select state
     int32_t *gT, *gK;      // fast variant: the global cut [64]
     struct SideArrays {
+        uint32_t *uT;      // UNIF: per-row cut of the draw
+        int32_t *uK;
         int32_t *pair_slot, *pair_chunk, *cutT, *cutK, *flag;
         int64_t *pair_off;
     } side[2];
@@ -131,6 +133,9 @@ Layout carve(const als_problem &p, void *base) {
         L.side[sd].cutT = c.take<int32_t>((size_t)hb * cut_stride(p));
         L.side[sd].cutK = c.take<int32_t>((size_t)hb * cut_stride(p));
         L.side[sd].flag = c.take<int32_t>((size_t)hb);
+        const bool unif = (p.flags & ALS_UNIF) != 0;
+        L.side[sd].uT = c.take<uint32_t>(unif ? (size_t)nr : 0);
+        L.side[sd].uK = c.take<int32_t>(unif ? (size_t)nr : 0);
     }
     size_t tb = own_csc ? csc_temp_bytes(p.nnz, p.n_m) : 0;
     size_t tp = perm_temp_bytes(uo ? p.n_u : std::max(p.n_u, p.n_m));
@@ -223,7 +228,34 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         HIP_CHECK(c, launch_sweep_fast(a, c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(ml));
     }
-    for (int cls = 0; cls < CLS_HEAVY && !c->fast; ++cls) {
+    if (c->unif) {
+        if (chk) return fail(c, ALS_E_STATE, "fold-in answers need the per-row method%s");
+        // every row's uniform draw, then every light row in one launch
+        als_ctx::Mark mg{}, ml{};
+        HIP_CHECK(c, mark_begin(PROF_HSELECT, mg));
+        HIP_CHECK(c, launch_unif_select(S.ptr, S.idx, S.n_rows, S.n_other, c->p.budget_num, c->p.budget_den,
+                                        c->p.min_keep, c->seed, c->uT[side], c->uK[side], c->stream));
+        HIP_CHECK(c, mark_end(mg));
+        SweepArgs a{};
+        a.ptr = S.ptr;
+        a.idx = S.idx;
+        a.val = S.val;
+        a.other = other;
+        a.out = out;
+        a.perm = S.perm;
+        a.count = S.class_off[CLS_HEAVY];
+        a.nf = c->p.n_f;
+        a.lam = (float)c->p.lambda;
+        a.num = c->p.budget_num;
+        a.den = c->p.budget_den;
+        a.min_keep = c->p.min_keep;
+        a.stats = sc.stats;
+        a.queue = queues;
+        HIP_CHECK(c, mark_begin(CLS_FULL, ml));
+        HIP_CHECK(c, launch_sweep_unif(a, c->seed, S.n_other, c->uT[side], c->uK[side], c->light_blocks, c->stream));
+        HIP_CHECK(c, mark_end(ml));
+    }
+    for (int cls = 0; cls < CLS_HEAVY && !c->fast && !c->unif; ++cls) {
         SweepArgs a{};
         a.ptr = S.ptr;
         a.idx = S.idx;
@@ -280,6 +312,11 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.flag = c->flag[side];
         h.pass = 0;
         h.gpos = 0;
+        h.unif = c->unif ? 1 : 0;
+        h.seed = c->seed;
+        h.n_cols = S.n_other;
+        h.uT = c->uT[side];
+        h.uK = c->uK[side];
         if (c->fast) {
             // one cut per column for every heavy row, ties by row index
             h.gpos = 1;
@@ -298,7 +335,7 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.tol = 0.f;
         h.path = nullptr;
         h.rho = nullptr;
-        if (c->p.budget_num < c->p.budget_den && !c->fast) {
+        if (c->p.budget_num < c->p.budget_den && !c->fast && !c->unif) {
             if (c->key16 && h.other_rows > 0 && h.other_rows * h.nf * 4 <= (int64_t)0x7FFFFFFF) {
                 // (the selection reads the copy only where it gathers by buffer loads)
                 HIP_CHECK(c, launch_key16(other, h.other_rows * h.nf, c->key16, c->stream));
@@ -403,7 +440,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
     if (other == out) return fail(c, ALS_E_ARG, "input and output factor matrices alias%s");
     if (c->use_graphs && !c->profiling) {
         als_ctx::Graph &G = c->graph[side];
-        if (!G.exec || G.other != other || G.out != out) {
+        if (!G.exec || G.other != other || G.out != out || G.seed != c->seed) {
             if (G.exec) {
                 (void)hipGraphExecDestroy(G.exec);
                 G.exec = nullptr;
@@ -422,6 +459,7 @@ als_status run_half_sweep(als_ctx *c, int side, const float *other, float *out, 
             HIP_CHECK(c, ei);
             G.other = other;
             G.out = out;
+            G.seed = c->seed;
         }
         HIP_CHECK(c, hipGraphLaunch(G.exec, c->stream));
     } else {
@@ -490,6 +528,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (p->budget_den == 0 || p->budget_num == 0 || p->budget_num > p->budget_den)
         return fail(nullptr, ALS_E_ARG, "budget rate must satisfy 0 < num <= den%s");
     if (p->min_keep < 0) return fail(nullptr, ALS_E_ARG, "min_keep must be >= 0%s");
+    if ((p->flags & ALS_UNIF) &&
+        (p->n_f > NF || p->precision != ALS_PREC_FP32 || (p->flags & ALS_FAST_VARIANT)))
+        return fail(nullptr, ALS_E_ARG, "UNIF needs n_f <= 64, FP32 and not the fast variant%s");
     if ((p->flags & ALS_FAST_VARIANT) &&
         (p->n_f > NF || p->precision != ALS_PREC_FP32 || (p->flags & ALS_USERS_ONLY)))
         return fail(nullptr, ALS_E_ARG, "the fast variant needs n_f <= 64, FP32 and both sides%s");
@@ -520,7 +561,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->partials = L.partials;
     c->resid = L.resid;
     c->fast = (p->flags & ALS_FAST_VARIANT) != 0;
-    c->key16 = p->budget_num < p->budget_den && !c->fast ? L.key16 : nullptr;
+    c->unif = (p->flags & ALS_UNIF) != 0;
+    c->key16 = p->budget_num < p->budget_den && !c->fast && !c->unif ? L.key16 : nullptr;
     c->gsel = L.gsel;
     c->gT = L.gT;
     c->gK = L.gK;
@@ -621,6 +663,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         H.cutT = L.side[sd].cutT;
         H.cutK = L.side[sd].cutK;
         c->flag[sd] = L.side[sd].flag;
+        c->uT[sd] = L.side[sd].uT;
+        c->uK[sd] = L.side[sd].uK;
         if (H.n_heavy == 0) continue;
         if (H.n_heavy > heavy_bound(*p, S.n_rows)) return bail(ALS_E_STATE, "heavy-row bound violated");
         std::vector<int32_t> rows((size_t)H.n_heavy);
@@ -818,6 +862,12 @@ als_status als_class_counts(const als_ctx *c, int64_t *out) {
     if (!c || !out) return ALS_E_STATE;
     for (int sd = 0; sd < 2; ++sd)
         for (int k = 0; k < NCLASS; ++k) out[sd * NCLASS + k] = c->side[sd].class_off[k + 1] - c->side[sd].class_off[k];
+    return ALS_OK;
+}
+
+als_status als_set_sample_seed(als_ctx *c, uint64_t seed) {
+    if (!c) return ALS_E_STATE;
+    c->seed = seed;
     return ALS_OK;
 }
 

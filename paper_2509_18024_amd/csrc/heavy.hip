@@ -487,7 +487,8 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         const int64_t beg = a.ptr[i];
         const int n = (int)(a.ptr[i + 1] - beg);
         const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
-        const float lamn = (float)((double)a.lam * (double)n);
+        // UNIF: lambda times the sample size (the subsample's own system)
+        const float lamn = (float)((double)a.lam * (double)(a.unif ? s : n));
         // the first pair's partial slot holds the kept LU factors between the
         // two solves (its partial system has been summed by then)
         // (fast variant: every row's sketch is a core system)
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         }
         finish_system(A, rhs, lamn, lane, a.nf);
         float u = 0.f;
-        const bool core = a.gpos || s < n;
+        const bool core = !a.unif && (a.gpos || s < n);
         bool ok;
         if (a.keep) {
             // a refinement step follows: keep the factors for it
@@ -544,6 +545,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         }
         if (!ok) {
             u = 0.f;
+            if (a.unif && lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);  // singular sample system
             if (core) {
                 // singular core system: full-data update of eq. (U)
                 if (lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
@@ -726,7 +728,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 
 // GPOS (fast variant): one cut per column for every row (cstride 0), its tie
 // rule applied to the entry's row index in `other` instead of its position.
-template <bool BUF, bool GPOS>
+// UNIF: entries outside the row's uniform draw are zeroed (both operands and
+// the right-hand side), every remaining entry kept.
+template <bool BUF, bool GPOS, bool UNIF>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_x6(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
@@ -755,14 +759,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
         // kept(k) <=> (key, ~k) >= (T, ~K) as unsigned 64-bit pairs; every
         // entry is kept with (T, K) = (0, INT_MAX), none with s = 0
         int T0 = 0, K0 = 0x7FFFFFFF, T1 = 0, K1 = 0x7FFFFFFF;
-        if (GPOS || s < n) {
+        const uint32_t uT = UNIF ? a.uT[i] : 0u;
+        const int uK = UNIF ? a.uK[i] : 0;
+        if (!UNIF && (GPOS || s < n)) {
             const int64_t cb = slot * (int64_t)a.cstride;
             T0 = a.cutT[cb + m];
             K0 = a.cutK[cb + m];
             T1 = a.cutT[cb + 32 + m];
             K1 = a.cutK[cb + 32 + m];
         }
-        if (!GPOS && s == 0) {
+        if (!UNIF && !GPOS && s == 0) {
             T0 = T1 = 0x7FFFFFFF;
             K0 = K1 = -1;
         }
@@ -818,6 +824,18 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                     }
                 // every gather of the batch is issued before the first use
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (UNIF) {
+#pragma unroll
+                    for (int st = 0; st < GX_STEPS; ++st)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int pos = e0 + 16 * st + 8 * h + e;
+                            const uint32_t key = unif_key(a.seed, i, a.n_cols, cols[st][e]);
+                            const bool kp = key < uT || (key == uT && pos <= uK);
+                            x0[st][e] = kp ? x0[st][e] : 0.f;
+                            x1[st][e] = kp ? x1[st][e] : 0.f;
+                        }
+                }
 #pragma unroll
                 for (int st = 0; st < GX_STEPS; ++st) {
                     const uint32_t nkb = ~(uint32_t)(e0 + 16 * st + 8 * h);  // ~k of the lane's first entry
@@ -1138,14 +1156,22 @@ hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pai
     const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
                      a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
     const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
-    if (buf && a.gpos)
-        hipLaunchKernelGGL((k_heavy_gram_x6<true, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    if (buf && a.unif)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+    else if (buf && a.gpos)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, true, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
     else if (buf)
-        hipLaunchKernelGGL((k_heavy_gram_x6<true, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, false, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
+    else if (a.unif)
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
     else if (a.gpos)
-        hipLaunchKernelGGL((k_heavy_gram_x6<false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, true, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
     else
-        hipLaunchKernelGGL((k_heavy_gram_x6<false, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, false, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
     return hipGetLastError();
 }
 

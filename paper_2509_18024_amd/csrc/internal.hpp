@@ -191,6 +191,11 @@ struct HeavyArgs {
     int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // Fp64Mode of the refinement residual
     int32_t *flag;            // per heavy slot: 0, or the pass that redoes the row
+    int32_t unif;             // UNIF: entries outside the row's uniform draw are zeroed
+    uint64_t seed;            //   (key = unif_key(seed, row, n_cols, col) against the
+    int64_t n_cols;           //   row's cut uT / uK), lambda s on the diagonal
+    const uint32_t *uT;
+    const int32_t *uK;
     int32_t gpos;             // fast variant: one cut per column (cstride 0), ties
                               // decided by the row index of `other`, not the position
     int32_t pass;             // 0: all rows; 1 (wide ranks): rows with a singular core
@@ -262,6 +267,13 @@ hipError_t launch_global_select(const float *other, int64_t n_other, int nf, uin
 // light rows of the fast variant (sweep.hip): every class, one kernel
 hipError_t launch_sweep_fast(const SweepArgs &a, int max_blocks, hipStream_t s);
 
+// UNIF (unif.hip): each row's cut of the uniform draw, the light rows
+hipError_t launch_unif_select(const int64_t *ptr, const int32_t *idx, int64_t n_rows, int64_t n_cols, uint32_t num,
+                              uint32_t den, int32_t min_keep, uint64_t seed, uint32_t *T, int32_t *K,
+                              hipStream_t s);
+hipError_t launch_sweep_unif(const SweepArgs &a, uint64_t seed, int64_t n_cols, const uint32_t *T, const int32_t *K,
+                             int max_blocks, hipStream_t s);
+
 // launchers (setup.hip)
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 size_t csc_temp_bytes(int64_t nnz, int64_t n_rows);
@@ -309,6 +321,10 @@ struct als_ctx {
     int fp64res = 0;       // Fp64Mode of the refinement residual
     bool wide = false;     // 64 < n_f <= NFW: wide-rank kernels for every row
     bool fast = false;     // ALS_FAST_VARIANT: one global sketch per half-sweep
+    bool unif = false;     // ALS_UNIF: uniform subsampling (the comparator)
+    uint64_t seed = 0;     // UNIF draws (als_set_sample_seed)
+    uint32_t *uT[2] = {nullptr, nullptr};  // UNIF: per-row cut of each side
+    int32_t *uK[2] = {nullptr, nullptr};
     void *gsel = nullptr;  // fast variant: radix-select state and the cut
     int32_t *gT = nullptr, *gK = nullptr;
     int32_t *flag[2] = {nullptr, nullptr};  // per heavy slot: the pass that redoes the row
@@ -327,6 +343,7 @@ struct als_ctx {
         hipGraphExec_t exec = nullptr;
         const float *other = nullptr;
         float *out = nullptr;
+        uint64_t seed = 0;  // UNIF draws are part of the captured launches
     };
     bool use_graphs = false;
     Graph graph[2];

@@ -33,6 +33,16 @@ __device__ __forceinline__ float wave_max(float v) {
 
 __device__ __forceinline__ int key_of(float x) { return __float_as_int(x) & KEYMASK; }
 
+// Key of entry (row, col) in the UNIF draw of a seed: the upper 32 bits of
+// splitmix64 (Steele, Lea and Flood, 2014) at seed * 0x9E3779B97F4A7C15 +
+// row * n_cols + col.  A row's draw keeps its budget of smallest keys.
+__device__ __forceinline__ uint32_t unif_key(uint64_t seed, int64_t row, int64_t n_cols, int32_t col) {
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t)(row * n_cols + (int64_t)col) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+
 // The lane index as a value the compiler cannot hoist out of a row loop.
 // Without it, the 64 per-step lane comparisons of the solve are precomputed
 // once per kernel as scalar masks and spilled.
