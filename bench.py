@@ -320,6 +320,70 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
     }
 
 
+def section5_report(torch, stream, dev, iters=10):
+    """The paper's simulation study on the GPU (Section 5): CORE, its fast
+    variant and UNIF against full ALS.  Timing in the setting of Table 1
+    (5000 x 5000, n_f = 50, lambda = 0.05; density and iteration count are
+    not stated there: half the entries observed, 10 iterations), accuracy
+    (ReMSE on the observed entries, P-ReMSE on a uniform sample of 1M held-out
+    entries) for D1/D2/D3 at 3600 x 3600, n_f = 60."""
+    from paper_2509_18024_amd import synth
+    from paper_2509_18024_amd.als import CoreALS
+
+    def run(prob, held, method, r):
+        budget = (1, 1) if method == "full" else r
+        rp, ci, v = (torch.from_numpy(x).to(dev) for x in (prob.row_ptr, prob.col_idx, prob.val))
+        hrp, hci, hv = (torch.from_numpy(x).to(dev) for x in held)
+        with torch.cuda.stream(stream):
+            als = CoreALS(prob.n_u, prob.n_m, prob.n_f, rp, ci, v, prob.lam, budget, 1, 0, stream=stream,
+                          fast=(method == "core_fast"), unif=(method == "unif"))
+            hq = CoreALS(prob.n_u, prob.n_m, prob.n_f, hrp, hci, hv, prob.lam, (1, 1), 1, 0, stream=stream,
+                         validate=False)
+            M = torch.from_numpy(prob.M0).to(dev)
+            U = torch.empty(prob.n_u, prob.n_f, dtype=torch.float32, device=dev)
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for t in range(iters):
+                if method == "unif":
+                    als.set_sample_seed(2 * t)
+                als.half_sweep_users(M, U)
+                if method == "unif":
+                    als.set_sample_seed(2 * t + 1)
+                als.half_sweep_items(U, M)
+            e1.record(stream)
+            stream.synchronize()
+            ms = e0.elapsed_time(e1)
+            obs = als.objective(U, M)
+            pred = hq.objective(U, M)
+            als.close()
+            hq.close()
+        return {"total_ms": ms, "ms_per_iteration": ms / iters, "remse": obs["remse"], "p_remse": pred["remse"]}
+
+    rates = [(1, 10), (3, 20), (1, 5), (1, 4)]
+    out = {"iterations": iters}
+    prob, held = synth.section5("D1", 5000, 5000, 50, 0.5, 0.05)
+    log(f"section 5: table-1 setting n={prob.n_u}x{prob.n_m} nnz={prob.nnz} n_f={prob.n_f}")
+    t1 = {"workload": f"D1 5000x5000, n_f=50, lambda=0.05, {prob.nnz} observed (half), {iters} iterations",
+          "full": run(prob, held, "full", None)}
+    for m in ("core", "core_fast", "unif"):
+        for r in rates:
+            t1[f"{m}_r{r[0]}/{r[1]}"] = run(prob, held, m, r)
+    t1["speedup_vs_full"] = {k: t1["full"]["total_ms"] / v["total_ms"] for k, v in t1.items()
+                             if isinstance(v, dict) and "total_ms" in v}
+    out["table1_setting"] = t1
+    log(f"section 5 timing: {json.dumps(t1)}")
+    acc = {}
+    for dist in ("D1", "D2", "D3"):
+        prob, held = synth.section5(dist, 3600, 3600, 60, 0.5, 0.05, seed=610 + int(dist[1]))
+        acc[dist] = {"full": run(prob, held, "full", None)}
+        for m in ("core", "core_fast", "unif"):
+            acc[dist][f"{m}_r1/10"] = run(prob, held, m, (1, 10))
+        log(f"section 5 accuracy {dist}: {json.dumps(acc[dist])}")
+    out["accuracy_3600_nf60"] = acc
+    return out
+
+
 # HIP kernel behind each timed group (group 8 is k_heavy_gram_bf16 in the BF16 modes)
 KERNEL_OF_GROUP = ["k_sweep_full"] + [f"k_sweep_core<{c}>" for c in range(1, 7)] + [
     "k_heavy_select", "k_heavy_gram_x6", "k_heavy_solve", "k_heavy_resid", "k_heavy_refine"]
@@ -376,6 +440,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
     ap.add_argument("--no-foldin", action="store_true", help="skip the learned fold-in section")
+    ap.add_argument("--no-section5", action="store_true", help="skip the simulation-study section")
     ap.add_argument("--foldin-epochs", type=int, default=5)
     ap.add_argument("--foldin-new-users", type=int, default=100_000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -502,6 +567,12 @@ def main():
             parity = sampled_parity(torch, head_als, prob, dev)
         log(f"parity: {parity}")
     head_als.close()
+    del head_als
+    torch.cuda.empty_cache()
+
+    sec5 = None
+    if not args.no_section5 and not args.headline_only:
+        sec5 = section5_report(torch, stream, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -544,6 +615,7 @@ def main():
         "per_kernel": per_kernel,
         "parity_sampled_full_size": parity,
         "foldin": foldin,
+        "section5": sec5,
     }
     print(json.dumps(line), flush=True)
 

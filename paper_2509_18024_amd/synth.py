@@ -367,6 +367,51 @@ def c4_precision(scale: float = 1.0, seed: int = 401, m0_seed: int = 402,
                    budget[0], budget[1], 1, 10, init_factors(m0_seed, n_m, n_f), U0, V0)
 
 
+def section5_factors(rng: np.random.Generator, n: int, n_f: int, dist: str) -> np.ndarray:
+    """Factor rows of the simulation study (Section 5.1): D1 multivariate
+    normal N(0, S), D2 multivariate log-normal LN(0, S) = exp of D1, D3
+    multivariate t with 4 degrees of freedom, with S_ij = 0.6^|i - j|."""
+    idx = np.arange(n_f)
+    S = 0.6 ** np.abs(idx[:, None] - idx[None, :])
+    Z = rng.standard_normal((n, n_f)) @ np.linalg.cholesky(S).T
+    if dist == "D1":
+        return Z
+    if dist == "D2":
+        return np.exp(Z)
+    if dist == "D3":
+        return Z / np.sqrt(rng.chisquare(4.0, size=(n, 1)) / 4.0)
+    raise ValueError(dist)
+
+
+def section5(dist: str = "D1", n_u: int = 5000, n_m: int = 5000, n_f: int = 50, alpha: float = 0.5,
+             lam: float = 0.05, seed: int = 601, m0_seed: int = 602, n_heldout: int = 1_000_000):
+    """The simulation workload of Section 5.1: R0 = U M^T from D1/D2/D3 factors,
+    N(0, 1) noise on every entry, a fraction alpha of the entries observed
+    (the rest, the prediction set I^c, set to NaN in the paper).  Returns the
+    observed problem and a uniform sample of held-out entries (CSR over the
+    same users) for the prediction error P-ReMSE."""
+    rng = np.random.default_rng(seed)
+    U0 = section5_factors(rng, n_u, n_f, dist)
+    V0 = section5_factors(rng, n_m, n_f, dist)
+    mask = rng.random((n_u, n_m)) < alpha
+    rows, cols = np.nonzero(mask)
+    row_ptr = np.zeros(n_u + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n_u), out=row_ptr[1:])
+    col_idx = cols.astype(np.int32)
+    val = (low_rank_values(U0, V0, row_ptr, col_idx) + rng.normal(0.0, 1.0, size=len(col_idx))).astype(np.float32)
+    prob = Problem(f"section5_{dist}", n_u, n_m, n_f, row_ptr, col_idx, val, lam, 1, 10, 1, 10,
+                   init_factors(m0_seed, n_m, n_f), U0, V0)
+    hr, hc = np.nonzero(~mask)
+    if len(hr) > n_heldout:
+        pick = np.sort(rng.choice(len(hr), size=n_heldout, replace=False))
+        hr, hc = hr[pick], hc[pick]
+    h_ptr = np.zeros(n_u + 1, dtype=np.int64)
+    np.cumsum(np.bincount(hr, minlength=n_u), out=h_ptr[1:])
+    h_idx = hc.astype(np.int32)
+    h_val = (low_rank_values(U0, V0, h_ptr, h_idx) + rng.normal(0.0, 1.0, size=len(h_idx))).astype(np.float32)
+    return prob, (h_ptr, h_idx, h_val)
+
+
 def c5_heldout(base: Problem, n_new: int, seed: int = 502):
     """New users for fold-in: fresh user factors, the item side of `base`,
     degrees from the same Lomax law, values UV' + N(0, 0.25)."""
