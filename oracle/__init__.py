@@ -86,6 +86,13 @@ def lib():
         L.ora_unif_half_sweep.argtypes = [ctypes.c_int64, ctypes.c_int32, I64P, I32P, F32P, ctypes.c_int64,
                                           F64P, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_uint64, F64P, I64P]
+        L.ora_global_gram.argtypes = [ctypes.c_int64, ctypes.c_int32, F64P, F64P]
+        L.ora_implicit_row.restype = ctypes.c_int
+        L.ora_implicit_row.argtypes = [ctypes.c_int64, ctypes.c_int32, F64P, F64P, F64P, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int64, F64P]
+        L.ora_implicit_half_sweep.argtypes = [ctypes.c_int64, ctypes.c_int32, I64P, I32P, F32P, ctypes.c_int64,
+                                              F64P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                              ctypes.c_int64, ctypes.c_int64, F64P, I64P]
         _lib = L
     return _lib
 
@@ -269,6 +276,34 @@ def unif_half_sweep(row_ptr, col_idx, val, other, lam, num, den, min_keep, seed)
     lib().ora_unif_half_sweep(n_rows, nf, _p(rp, I64P), _p(ci, I32P), _p(v, F32P), O.shape[0], _p(O, F64P),
                               float(lam), int(num), int(den), int(min_keep), ctypes.c_uint64(seed),
                               _p(out, F64P), _p(st, I64P))
+    return out, st
+
+
+def implicit_row(X, r, G, lam, alpha, s):
+    """Implicit-feedback core regression (reading of Section 3's last
+    paragraph): (G + X*^T W X + lambda E) u = X*^T (1 + alpha r), W = diag(alpha r),
+    G = Y^T Y.  Returns (u, status)."""
+    X = _c(X, np.float64)
+    r = _c(r, np.float64)
+    G = _c(G, np.float64)
+    n, nf = X.shape
+    u = np.zeros(nf, np.float64)
+    st = lib().ora_implicit_row(n, nf, _p(X, F64P), _p(r, F64P), _p(G, F64P), float(lam), float(alpha), int(s),
+                                _p(u, F64P))
+    return u, st
+
+
+def implicit_half_sweep(row_ptr, col_idx, val, other, lam, alpha, num, den, min_keep):
+    """One implicit-feedback Core-ALS half-sweep.  Returns (out, stats)."""
+    rp, ci, v = _c(row_ptr, np.int64), _c(col_idx, np.int32), _c(val, np.float32)
+    O = _c(other, np.float64)
+    n_rows = len(rp) - 1
+    nf = O.shape[1]
+    out = np.zeros((n_rows, nf), np.float64)
+    st = np.zeros(2, np.int64)
+    lib().ora_implicit_half_sweep(n_rows, nf, _p(rp, I64P), _p(ci, I32P), _p(v, F32P), O.shape[0], _p(O, F64P),
+                                  float(lam), float(alpha), int(num), int(den), int(min_keep), _p(out, F64P),
+                                  _p(st, I64P))
     return out, st
 
 

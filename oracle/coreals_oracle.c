@@ -18,6 +18,7 @@
  *                                                          (Section 3, eq. core_ui/core_mj)
  *  - one half-sweep of Core-ALS over all rows              (Section 3, Algorithm 2)
  *  - UNIF, the uniform-subsampling comparator           (Section 5, Tables 1, 2)
+ *  - implicit-feedback Core-ALS                          (Section 3, last paragraph)
  *  - the fast variant: CES once per half-sweep on the whole factor matrix of
  *    the other side, each row regressing on that global sketch
  *                                                          (Section 3, the paragraph
@@ -609,5 +610,103 @@ void ora_unif_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr, con
     if (stats) {
         stats[0] = n_empty;
         stats[1] = n_sing;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Implicit-feedback Core-ALS (Section 3, last paragraph; the paper defers its
+ * form to the appendix, which is not in the text).  Reading: the implicit
+ * ALS of Hu, Koren and Volinsky (2008) with the core-elements sketch on the
+ * observed part.  Every observed entry is a preference 1 with confidence
+ * c = 1 + alpha r; every other entry a preference 0 with confidence 1.  The
+ * full-data update of row i, (Y^T C_i Y + lambda E) u = Y^T C_i p_i, splits as
+ * Y^T Y + X^T W X with X the row's observed rows of Y and W = diag(alpha r_k);
+ * the core version sketches the observed part:
+ *     (Y^T Y + X*^T W X + lambda E) u = X*^T (1 + alpha r),
+ * X* = CES(X, r) column by column as in Algorithm 1.  At r = 1 it is implicit
+ * ALS exactly.
+ * ---------------------------------------------------------------------- */
+
+/* G = other^T other (n_other x nf, row-major), the Gram over all rows. */
+void ora_global_gram(int64_t n_other, int32_t nf, const double *other, double *G) {
+    for (int32_t a = 0; a < nf; ++a)
+        for (int32_t c = 0; c < nf; ++c) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < n_other; ++j) acc += other[j * nf + a] * other[j * nf + c];
+            G[a * nf + c] = acc;
+        }
+}
+
+/* One implicit core regression.  Status: 1 empty row (u = 0: b = 0), 2
+ * singular core system replaced by the full-data implicit update, 3 singular
+ * with s = n (u = 0). */
+int ora_implicit_row(int64_t n, int32_t nf, const double *X, const double *r, const double *G, double lam,
+                     double alpha, int64_t s, double *u) {
+    if (n == 0) {
+        for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+        return 1;
+    }
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)nf * (size_t)(s > 0 ? s : 1));
+    ora_select(n, nf, X, s, pos);
+    double *A = (double *)malloc(sizeof(double) * (size_t)nf * nf);
+    double *b = (double *)calloc((size_t)nf, sizeof(double));
+    int status = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int64_t e = 0; e < (int64_t)nf * nf; ++e) A[e] = G[e];
+        for (int32_t a = 0; a < nf; ++a) {
+            b[a] = 0.0;
+            const int64_t cnt = attempt == 0 ? s : n;
+            for (int64_t t = 0; t < cnt; ++t) {
+                int64_t k = attempt == 0 ? pos[a * s + t] : t;
+                double xa = X[k * nf + a];
+                for (int32_t c = 0; c < nf; ++c) A[a * nf + c] += alpha * r[k] * xa * X[k * nf + c];
+                b[a] += (1.0 + alpha * r[k]) * xa;
+            }
+            A[a * nf + a] += lam;
+        }
+        double amax = 0.0;
+        for (int64_t e = 0; e < (int64_t)nf * nf; ++e) amax = fmax(amax, fabs(A[e]));
+        if (!ora_gepp(nf, A, b, (double)nf * ldexp(1.0, -52) * amax)) {
+            for (int32_t a = 0; a < nf; ++a) u[a] = b[a];
+            break;
+        }
+        if (attempt == 1 || s >= n) {
+            for (int32_t a = 0; a < nf; ++a) u[a] = 0.0;
+            status = s >= n ? 3 : 2;
+            break;
+        }
+        status = 2;
+    }
+    free(A);
+    free(b);
+    free(pos);
+    return status;
+}
+
+/* One implicit half-sweep: G = other^T other, then every row.  stats[0]
+ * empty rows, stats[1] singular core systems replaced by the full data. */
+void ora_implicit_half_sweep(int64_t n_rows, int32_t nf, const int64_t *row_ptr, const int32_t *col_idx,
+                             const float *val, int64_t n_other, const double *other, double lam, double alpha,
+                             int64_t num, int64_t den, int64_t min_keep, double *out, int64_t *stats) {
+    double *G = (double *)malloc(sizeof(double) * (size_t)nf * nf);
+    ora_global_gram(n_other, nf, other, G);
+    int64_t n_empty = 0, n_fallback = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_empty, n_fallback)
+    for (int64_t i = 0; i < n_rows; ++i) {
+        int64_t beg = row_ptr[i];
+        int64_t n = row_ptr[i + 1] - beg;
+        double *X = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nf);
+        double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        ora_gather(beg, n, nf, col_idx, val, other, X, y);
+        int st = ora_implicit_row(n, nf, X, y, G, lam, alpha, ora_budget(n, num, den, min_keep), out + i * nf);
+        if (st == 1) n_empty++;
+        if (st == 2) n_fallback++;
+        free(X);
+        free(y);
+    }
+    free(G);
+    if (stats) {
+        stats[0] = n_empty;
+        stats[1] = n_fallback;
     }
 }

@@ -562,3 +562,51 @@ def test_unif_half_sweep_vs_dense(ora):
         ref = np.linalg.solve(X.T @ X + p.lam * s * np.eye(6), X.T @ y)
         assert np.allclose(out[i], ref, rtol=1e-10, atol=1e-12)
     assert st[1] == n_zero
+
+
+# ---------------------------------------------------------------- implicit feedback
+# (Section 3, last paragraph; reading: the implicit ALS of Hu, Koren and
+# Volinsky with the core sketch on the observed part)
+
+def test_implicit_full_budget_is_dense_implicit_als(ora):
+    """r = 1 against the implicit update written over every item, without the
+    Y^T Y split: (Y^T C_i Y + lambda E) u = Y^T C_i p_i with c = 1 + alpha r and
+    p = 1 on the observed items, c = 1 and p = 0 elsewhere."""
+    rng = np.random.default_rng(77)
+    p = synth.random_problem(77, 30, 25, 3, 0.3, budget=(1, 1))
+    val = np.abs(p.val).astype(np.float32)  # counts are non-negative
+    Y = rng.normal(0, 1, (p.n_m, p.n_f))
+    lam, alpha = 0.1, 2.0
+    out, st = ora.implicit_half_sweep(p.row_ptr, p.col_idx, val, Y, lam, alpha, 1, 1, 1)
+    for i in range(p.n_u):
+        c = np.ones(p.n_m)
+        pref = np.zeros(p.n_m)
+        cols = p.col_idx[p.row_ptr[i]:p.row_ptr[i + 1]]
+        c[cols] = 1 + alpha * val[p.row_ptr[i]:p.row_ptr[i + 1]]
+        pref[cols] = 1.0
+        A = Y.T @ (c[:, None] * Y) + lam * np.eye(p.n_f)
+        ref = np.linalg.solve(A, Y.T @ (c * pref))
+        assert np.allclose(out[i], ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("num,den", [(1, 10), (1, 3)])
+def test_implicit_core_vs_dense_sketch(ora, num, den):
+    """r < 1: the sketch X* built explicitly (independent key sort), then
+    (Y^T Y + X*^T W X + lambda E) u = X*^T (1 + alpha r) by LAPACK."""
+    rng = np.random.default_rng(78 + den)
+    p = synth.random_problem(78 + den, 40, 60, 4, 0.4, budget=(num, den))
+    val = np.abs(p.val).astype(np.float32)
+    Y = rng.normal(0, 1, (p.n_m, p.n_f))
+    lam, alpha = 0.05, 1.5
+    out, st = ora.implicit_half_sweep(p.row_ptr, p.col_idx, val, Y, lam, alpha, num, den, 1)
+    G = Y.T @ Y
+    for i in range(p.n_u):
+        b, e = p.row_ptr[i], p.row_ptr[i + 1]
+        X = Y[p.col_idx[b:e]]
+        r = val[b:e].astype(np.float64)
+        s = max(1, (e - b) * num // den)
+        Xs = np.where(brute_mask(X, s), X, 0.0)
+        A = G + Xs.T @ (alpha * r[:, None] * X) + lam * np.eye(p.n_f)
+        ref = np.linalg.solve(A, Xs.T @ (1 + alpha * r))
+        assert np.allclose(out[i], ref, rtol=1e-9, atol=1e-11)
+    assert st[1] == 0
