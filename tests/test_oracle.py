@@ -582,7 +582,7 @@ def test_implicit_full_budget_is_dense_implicit_als(ora):
         c = np.ones(p.n_m)
         pref = np.zeros(p.n_m)
         cols = p.col_idx[p.row_ptr[i]:p.row_ptr[i + 1]]
-        c[cols] = 1 + alpha * val[p.row_ptr[i]:p.row_ptr[i + 1]]
+        c[cols] = 1 + alpha * val[p.row_ptr[i]:p.row_ptr[i + 1]].astype(np.float64)
         pref[cols] = 1.0
         A = Y.T @ (c[:, None] * Y) + lam * np.eye(p.n_f)
         ref = np.linalg.solve(A, Y.T @ (c * pref))
