@@ -96,6 +96,20 @@ typedef enum {
                         n_f <= 64, ALS_PREC_FP32, not ALS_FAST_VARIANT;
                         n_singular_fallback counts singular sample systems
                         (answered with u = 0) */
+#define ALS_IMPLICIT 32u /* implicit-feedback Core-ALS (Section 3, last
+                            paragraph; the form is a reading, the paper's
+                            appendix is not in its text): the ratings are
+                            confidences, every observed entry a preference 1
+                            with confidence 1 + alpha r, every other entry a
+                            preference 0 with confidence 1 (Hu, Koren and
+                            Volinsky); a row solves
+                            (Y^T Y + X*^T W X + lambda E) u = X*^T (1 + alpha r)
+                            with Y the whole other factor matrix, X its rows at
+                            the row's entries, W = diag(alpha r), X* = CES(X)
+                            (Algorithm 1).  r = 1 is implicit ALS.  Uses
+                            als_problem.alpha >= 0; needs n_f <= 64,
+                            ALS_PREC_FP32, not ALS_FAST_VARIANT / ALS_UNIF;
+                            objective returns ALS_E_STATE */
 #define ALS_GENERIC_GATHERS 4u /* heavy-row kernels gather with 64-bit addresses
                                  even where 32-bit buffer offsets would do (the
                                  path taken for factor matrices of 2^24 rows or
@@ -134,6 +148,7 @@ typedef struct {
                                     pointer until als_destroy                       */
     const int32_t *row_idx;
     const float *val_t;
+    double alpha;                /* ALS_IMPLICIT: confidence 1 + alpha r per rating */
 } als_problem;
 
 typedef struct {
@@ -191,7 +206,9 @@ als_status half_sweep_items(als_ctx *c, const float *U, float *M, als_sweep_stat
  * the first call on that GPU until the process ends, instead of in the
  * context's workspace.  It calls no allocator.  The context must have been
  * created with heavy_pair_cap <= half_sweep_noalloc_pair_cap() (1024);
- * ALS_E_ARG otherwise.  Results are identical to the workspace entry points'.
+ * ALS_E_ARG otherwise, and for contexts created with ALS_FAST_VARIANT,
+ * ALS_UNIF or ALS_IMPLICIT (their selection state and Gram stay in the
+ * workspace).  Results are identical to the workspace entry points'.
  * The array keeps the last call's contents and every call on a GPU shares
  * it: calls that overlap in time on one GPU (several streams or threads)
  * race.  Never captured into the context's graphs; no profiling marks.  st

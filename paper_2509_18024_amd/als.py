@@ -36,7 +36,8 @@ class CoreALS:
                  precision: int = capi.ALS_PREC_FP32, validate: bool = True, stream=None,
                  heavy_min_degree: int = 0, heavy_chunk: int = 0, heavy_pair_cap: int = 0,
                  light_blocks: int = 0, graphs: bool = False, users_only: bool = False,
-                 generic_gathers: bool = False, csc=None, fast: bool = False, unif: bool = False):
+                 generic_gathers: bool = False, csc=None, fast: bool = False, unif: bool = False,
+                 implicit_alpha: Optional[float] = None):
         capi.load()
         nnz = int(col_idx.numel())
         _need(row_ptr, torch.int64, n_u + 1, "row_ptr")
@@ -55,7 +56,9 @@ class CoreALS:
         p.precision = int(precision)
         p.flags = ((capi.ALS_VALIDATE if validate else 0) | (capi.ALS_USERS_ONLY if users_only else 0)
                    | (capi.ALS_GENERIC_GATHERS if generic_gathers else 0)
-                   | (capi.ALS_FAST_VARIANT if fast else 0) | (capi.ALS_UNIF if unif else 0))
+                   | (capi.ALS_FAST_VARIANT if fast else 0) | (capi.ALS_UNIF if unif else 0)
+                   | (capi.ALS_IMPLICIT if implicit_alpha is not None else 0))
+        p.alpha = float(implicit_alpha or 0.0)
         p.stream = self.stream.cuda_stream
         p.heavy_min_degree = int(heavy_min_degree)
         p.heavy_chunk = int(heavy_chunk)

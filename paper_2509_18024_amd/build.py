@@ -15,7 +15,8 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcoreals.so")
 SOURCES = ["capi.hip", "setup.hip", "sweep.hip", "heavy.hip", "wide.hip", "objective.hip", "foldin.hip",
-           "fast.hip", "unif.hip", "noalloc.hip"]
+           "fast.hip", "unif.hip", "implicit.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -20,6 +20,7 @@ ALS_USERS_ONLY = 2
 ALS_GENERIC_GATHERS = 4
 ALS_FAST_VARIANT = 8
 ALS_UNIF = 16
+ALS_IMPLICIT = 32
 FOLDIN_BF16, FOLDIN_FP32 = 0, 1
 
 STATUS_NAMES = {0: "ALS_OK", 1: "ALS_E_ARG", 2: "ALS_E_INDEX", 3: "ALS_E_VALUE", 4: "ALS_E_NOMEM",
@@ -39,6 +40,7 @@ class als_problem(ctypes.Structure):
         ("heavy_min_degree", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
         ("heavy_pair_cap", ctypes.c_int32), ("light_blocks", ctypes.c_int32),
         ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p), ("val_t", ctypes.c_void_p),
+        ("alpha", ctypes.c_double),
     ]
 
 

@@ -46,6 +46,8 @@ struct Layout {
     float *partials;
     double *resid;
     uint16_t *key16;
+    double *gram_part;     // implicit: per-block partial Grams
+    float *G;              // implicit: the Gram of the other factor matrix
     void *gsel;            // fast variant: radix-select state
     int32_t *gT, *gK;      // fast variant: the global cut [64]
     struct SideArrays {
@@ -122,6 +124,9 @@ Layout carve(const als_problem &p, void *base) {
     const bool fast = (p.flags & ALS_FAST_VARIANT) != 0;
     L.key16 = c.take<uint16_t>(p.budget_num < p.budget_den && !fast ? (size_t)other_max * p.n_f : 0);
     L.gsel = c.take<char>(fast ? global_select_state_bytes() : 0);
+    const bool impl = (p.flags & ALS_IMPLICIT) != 0;
+    L.gram_part = c.take<double>(impl ? (size_t)implicit_gram_blocks() * NF * NF : 0);
+    L.G = c.take<float>(impl ? (size_t)NF * NF : 0);
     L.gT = c.take<int32_t>(64);
     L.gK = c.take<int32_t>(64);
     for (int sd = 0; sd < 2; ++sd) {
@@ -255,6 +260,11 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         HIP_CHECK(c, launch_sweep_unif(a, c->seed, S.n_other, c->uT[side], c->uK[side], c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(ml));
     }
+    if (c->implicit) {
+        if (chk) return fail(c, ALS_E_STATE, "fold-in answers need explicit feedback%s");
+        // G = Y^T Y of the whole other factor matrix, shared by every row
+        HIP_CHECK(c, launch_global_gram(other, S.n_other, c->p.n_f, c->gram_part, c->G, c->stream));
+    }
     for (int cls = 0; cls < CLS_HEAVY && !c->fast && !c->unif; ++cls) {
         SweepArgs a{};
         a.ptr = S.ptr;
@@ -278,7 +288,10 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         if (a.count <= 0) continue;
         als_ctx::Mark mk{};
         HIP_CHECK(c, mark_begin(cls, mk));
+        a.alpha = (float)c->p.alpha;
+        a.G = c->G;
         if (c->wide) HIP_CHECK(c, launch_wide_empty(a, c->stream));  // the only light rows: no entries
+        else if (c->implicit) HIP_CHECK(c, launch_sweep_implicit(cls, a, c->light_blocks, c->stream));
         else if (chk) HIP_CHECK(c, launch_check_class(cls, a, c->light_blocks, c->stream));
         else HIP_CHECK(c, launch_sweep_class(cls, a, c->light_blocks, c->stream));
         HIP_CHECK(c, mark_end(mk));
@@ -312,6 +325,9 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.flag = c->flag[side];
         h.pass = 0;
         h.gpos = 0;
+        h.implicit = c->implicit ? 1 : 0;
+        h.alpha = (float)c->p.alpha;
+        h.G = c->G;
         h.unif = c->unif ? 1 : 0;
         h.seed = c->seed;
         h.n_cols = S.n_other;
@@ -528,6 +544,11 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     if (p->budget_den == 0 || p->budget_num == 0 || p->budget_num > p->budget_den)
         return fail(nullptr, ALS_E_ARG, "budget rate must satisfy 0 < num <= den%s");
     if (p->min_keep < 0) return fail(nullptr, ALS_E_ARG, "min_keep must be >= 0%s");
+    if ((p->flags & ALS_IMPLICIT) &&
+        (p->n_f > NF || p->precision != ALS_PREC_FP32 || (p->flags & (ALS_FAST_VARIANT | ALS_UNIF))))
+        return fail(nullptr, ALS_E_ARG, "implicit feedback needs n_f <= 64, FP32 and the per-row method%s");
+    if ((p->flags & ALS_IMPLICIT) && !(p->alpha >= 0.0))
+        return fail(nullptr, ALS_E_ARG, "alpha must be >= 0%s");
     if ((p->flags & ALS_UNIF) &&
         (p->n_f > NF || p->precision != ALS_PREC_FP32 || (p->flags & ALS_FAST_VARIANT)))
         return fail(nullptr, ALS_E_ARG, "UNIF needs n_f <= 64, FP32 and not the fast variant%s");
@@ -562,6 +583,9 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->resid = L.resid;
     c->fast = (p->flags & ALS_FAST_VARIANT) != 0;
     c->unif = (p->flags & ALS_UNIF) != 0;
+    c->implicit = (p->flags & ALS_IMPLICIT) != 0;
+    c->gram_part = L.gram_part;
+    c->G = L.G;
     c->key16 = p->budget_num < p->budget_den && !c->fast && !c->unif ? L.key16 : nullptr;
     c->gsel = L.gsel;
     c->gT = L.gT;
@@ -814,6 +838,7 @@ als_status core_select_global(als_ctx *c, int side, const float *other, int32_t 
 als_status objective(als_ctx *c, const float *U, const float *M, als_objective *out) {
     if (!c) return ALS_E_STATE;
     if (c->users_only) return fail(c, ALS_E_STATE, "context was created with ALS_USERS_ONLY%s");
+    if (c->implicit) return fail(c, ALS_E_STATE, "objective computes the explicit loss; context is ALS_IMPLICIT%s");
     if (!U || !M || !out) return fail(c, ALS_E_ARG, "NULL pointer%s");
     HIP_CHECK(c, launch_objective(c->p.n_u, c->p.n_m, c->p.n_f, c->p.row_ptr, c->p.col_idx, c->p.val, c->col_ptr, U,
                                   M, c->p.lambda, c->obj_partials, c->obj_out, c->stream));

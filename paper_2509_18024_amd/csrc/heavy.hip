@@ -503,7 +503,8 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
             for (int b = 0; b < NF; ++b) A[b] += src[b * 64 + lane];
             rhs += src[NF * 64 + lane];
         }
-        finish_system(A, rhs, lamn, lane, a.nf);
+        if (a.implicit) finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
+        else finish_system(A, rhs, lamn, lane, a.nf);
         float u = 0.f;
         const bool core = !a.unif && (a.gpos || s < n);
         bool ok;
@@ -551,8 +552,13 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
                 if (lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
                 RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
                 Cut full{0, 0, false, true};
-                gram(L, r, full, lane, A, rhs);
-                finish_system(A, rhs, lamn, lane, a.nf);
+                if (a.implicit) {
+                    gram_range_sparse<WaveLds, true>(L, r, full, 0, n, lane, A, rhs, a.alpha);
+                    finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
+                } else {
+                    gram(L, r, full, lane, A, rhs);
+                    finish_system(A, rhs, lamn, lane, a.nf);
+                }
                 ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
                 if (!ok) u = 0.f;
             }
@@ -730,7 +736,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 // rule applied to the entry's row index in `other` instead of its position.
 // UNIF: entries outside the row's uniform draw are zeroed (both operands and
 // the right-hand side), every remaining entry kept.
-template <bool BUF, bool GPOS, bool UNIF>
+// IMPL (implicit feedback): the kept operand is weighted by alpha y_k and the
+// right-hand side sums x_ka (1 + alpha y_k).
+template <bool BUF, bool GPOS, bool UNIF, bool IMPL = false>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_x6(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
@@ -840,12 +848,13 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                 for (int st = 0; st < GX_STEPS; ++st) {
                     const uint32_t nkb = ~(uint32_t)(e0 + 16 * st + 8 * h);  // ~k of the lane's first entry
                     uint32_t ph[2][4], pm[2][4], pl[2][4], mk[2][4];
+                    uint32_t wh[2][4], wm[2][4], wl[2][4];  // IMPL: parts of the weighted operand
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         const uint64_t bt = t ? b1 : b0;
 #pragma unroll
                         for (int e2 = 0; e2 < 4; ++e2) {
-                            float xv[2];
+                            float xv[2], xw[2];
                             uint32_t km[2];
 #pragma unroll
                             for (int o = 0; o < 2; ++o) {
@@ -858,8 +867,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                                 const bool kp = key >= bt;
                                 km[o] = kp ? 0xFFFFu : 0u;
                                 const float y = s_y[w][j0 + 16 * st + 8 * h + e];
-                                if (t) racc1 = fmaf(kp ? x : 0.f, y, racc1);
-                                else racc0 = fmaf(kp ? x : 0.f, y, racc0);
+                                if constexpr (IMPL) {
+                                    // X*^T W X: the kept operand carries the weight
+                                    const float yc = fmaf(a.alpha, y, 1.f);
+                                    if (t) racc1 = fmaf(kp ? x : 0.f, yc, racc1);
+                                    else racc0 = fmaf(kp ? x : 0.f, yc, racc0);
+                                    xw[o] = x * (a.alpha * y);
+                                } else {
+                                    if (t) racc1 = fmaf(kp ? x : 0.f, y, racc1);
+                                    else racc0 = fmaf(kp ? x : 0.f, y, racc0);
+                                }
                             }
                             // x = h + m + l, each part rounded to nearest from
                             // the exact remainder of the previous ones
@@ -873,6 +890,15 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                             pm[t][e2] = qm;
                             pl[t][e2] = pack_bf16(s0, s1);
                             mk[t][e2] = km[0] | (km[1] << 16);
+                            if constexpr (IMPL) {
+                                const uint32_t gh = pack_bf16(xw[0], xw[1]);
+                                const float g0 = xw[0] - __uint_as_float(gh << 16);
+                                const float g1 = xw[1] - __uint_as_float(gh & 0xFFFF0000u);
+                                const uint32_t gm = pack_bf16(g0, g1);
+                                wh[t][e2] = gh;
+                                wm[t][e2] = gm;
+                                wl[t][e2] = pack_bf16(g0 - __uint_as_float(gm << 16), g1 - __uint_as_float(gm & 0xFFFF0000u));
+                            }
                         }
                     }
                     // B operands (all entries) and A operands (kept entries only)
@@ -882,9 +908,9 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
                         uint32_t qh[4], qm[4], ql[4];
 #pragma unroll
                         for (int e2 = 0; e2 < 4; ++e2) {
-                            qh[e2] = ph[t][e2] & mk[t][e2];
-                            qm[e2] = pm[t][e2] & mk[t][e2];
-                            ql[e2] = pl[t][e2] & mk[t][e2];
+                            qh[e2] = (IMPL ? wh[t][e2] : ph[t][e2]) & mk[t][e2];
+                            qm[e2] = (IMPL ? wm[t][e2] : pm[t][e2]) & mk[t][e2];
+                            ql[e2] = (IMPL ? wl[t][e2] : pl[t][e2]) & mk[t][e2];
                         }
                         bh[t] = __builtin_bit_cast(bf16x8, ph[t]);
                         bm[t] = __builtin_bit_cast(bf16x8, pm[t]);
@@ -1156,7 +1182,13 @@ hipError_t launch_heavy_gram(const HeavyArgs &a, int64_t pair_begin, int64_t pai
     const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
                      a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
     const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
-    if (buf && a.unif)
+    if (buf && a.implicit)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, false, false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
+    else if (a.implicit)
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, false, false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin,
+                           pair_end);
+    else if (buf && a.unif)
         hipLaunchKernelGGL((k_heavy_gram_x6<true, false, true>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);
     else if (buf && a.gpos)
         hipLaunchKernelGGL((k_heavy_gram_x6<true, true, false>), grid, dim3(WPB * 64), 0, s, a, pair_begin, pair_end);

@@ -159,6 +159,9 @@ struct SweepArgs {
     // key == gT[a] and row index <= gK[a]) replaces each row's selection
     const int32_t *gT;
     const int32_t *gK;
+    // implicit feedback: confidence weight and the Gram of `other` (NF x NF)
+    float alpha;
+    const float *G;
 };
 
 struct HeavyArgs {
@@ -191,6 +194,9 @@ struct HeavyArgs {
     int32_t keep;             // first solve keeps its LU factors for the refinement step
     int32_t fp64res;          // Fp64Mode of the refinement residual
     int32_t *flag;            // per heavy slot: 0, or the pass that redoes the row
+    int32_t implicit;         // implicit feedback: X*^T W X + G + lambda E, W = alpha y
+    float alpha;
+    const float *G;           //   the Gram of `other`, NF x NF
     int32_t unif;             // UNIF: entries outside the row's uniform draw are zeroed
     uint64_t seed;            //   (key = unif_key(seed, row, n_cols, col) against the
     int64_t n_cols;           //   row's cut uT / uK), lambda s on the diagonal
@@ -267,6 +273,13 @@ hipError_t launch_global_select(const float *other, int64_t n_other, int nf, uin
 // light rows of the fast variant (sweep.hip): every class, one kernel
 hipError_t launch_sweep_fast(const SweepArgs &a, int max_blocks, hipStream_t s);
 
+// implicit feedback (implicit.hip): the Gram of `other` (float NF x NF, from
+// FP64 sums; partials: blocks x NF x NF doubles) and the light rows
+int implicit_gram_blocks();
+hipError_t launch_global_gram(const float *other, int64_t n_other, int nf, double *partials, float *G,
+                              hipStream_t s);
+hipError_t launch_sweep_implicit(int cls, const SweepArgs &a, int max_blocks, hipStream_t s);
+
 // UNIF (unif.hip): each row's cut of the uniform draw, the light rows
 hipError_t launch_unif_select(const int64_t *ptr, const int32_t *idx, int64_t n_rows, int64_t n_cols, uint32_t num,
                               uint32_t den, int32_t min_keep, uint64_t seed, uint32_t *T, int32_t *K,
@@ -322,6 +335,9 @@ struct als_ctx {
     bool wide = false;     // 64 < n_f <= NFW: wide-rank kernels for every row
     bool fast = false;     // ALS_FAST_VARIANT: one global sketch per half-sweep
     bool unif = false;     // ALS_UNIF: uniform subsampling (the comparator)
+    bool implicit = false; // ALS_IMPLICIT: implicit-feedback Core-ALS
+    double *gram_part = nullptr;  // implicit: per-block partial Grams
+    float *G = nullptr;           // implicit: the Gram of the other factor matrix
     uint64_t seed = 0;     // UNIF draws (als_set_sample_seed)
     uint32_t *uT[2] = {nullptr, nullptr};  // UNIF: per-row cut of each side
     int32_t *uK[2] = {nullptr, nullptr};

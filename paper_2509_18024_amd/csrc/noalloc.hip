@@ -70,10 +70,10 @@ int64_t half_sweep_noalloc_pair_cap(void) { return NA_PAIR_CAP; }
 als_status half_sweep_noalloc(als_ctx *c, int side, const float *other, float *out, als_sweep_stats *st) {
     if (!c) return ALS_E_STATE;
     if (side != 0 && side != 1) return set_error(c, ALS_E_ARG, "side must be 0 or 1");
-    if (c->fast || c->unif)
+    if (c->fast || c->unif || c->implicit)
         return set_error(c, ALS_E_ARG,
-                         "half_sweep_noalloc: the fast variant and UNIF keep their selection state in the "
-                         "workspace; use half_sweep_users / half_sweep_items");
+                         "half_sweep_noalloc: the fast variant, UNIF and implicit feedback keep their state "
+                         "(selection, Gram) in the workspace; use half_sweep_users / half_sweep_items");
     // partial systems of 65 x 64 floats (ranks up to 64) or 129 x 128 (above)
     const int64_t slot = c->wide ? (int64_t)(NFW + 1) * NFW : (int64_t)(NF + 1) * 64;
     if (c->pair_cap * slot > NA_PAIR_CAP * (NF + 1) * 64 || c->pair_cap * 2 * (c->wide ? NFW : 64) > NA_PAIR_CAP * 128)

@@ -333,9 +333,11 @@ __device__ __forceinline__ void gram_range(LDS &L, RowCtx &r, const Cut &c, int 
 // mask, then walks them in ascending order (the wave iterates as often as its
 // busiest lane).  Only the zero products of the unkept positions are skipped,
 // so the sums equal gram_range's.
-template <class LDS>
+// WEIGHTED (implicit feedback): row a of X*^T W X with W = diag(alpha y_k),
+// and b_a = sum over kept k of x_ka (1 + alpha y_k).
+template <class LDS, bool WEIGHTED = false>
 __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &c, int kb, int ke, int lane,
-                                                  float (&A)[NF], float &rhs) {
+                                                  float (&A)[NF], float &rhs, float alpha = 0.f) {
 #pragma unroll
     for (int b = 0; b < NF; ++b) A[b] = 0.f;
     rhs = 0.f;
@@ -350,7 +352,8 @@ __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &
             if (bits != 0ull) {
                 const int k = __ffsll((unsigned long long)bits) - 1;
                 bits &= bits - 1;
-                const float w = L.X[k][lane];
+                const float xk = L.X[k][lane];
+                const float w = WEIGHTED ? xk * (alpha * L.y[k]) : xk;
 #pragma unroll
                 for (int b4 = 0; b4 < NF / 4; ++b4) {
                     const float4 xr = *reinterpret_cast<const float4 *>(&L.X[k][b4 * 4]);
@@ -359,7 +362,7 @@ __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &
                     A[4 * b4 + 2] = fmaf(w, xr.z, A[4 * b4 + 2]);
                     A[4 * b4 + 3] = fmaf(w, xr.w, A[4 * b4 + 3]);
                 }
-                rhs = fmaf(w, L.y[k], rhs);
+                rhs = WEIGHTED ? fmaf(xk, fmaf(alpha, L.y[k], 1.f), rhs) : fmaf(w, L.y[k], rhs);
             }
         }
     }
@@ -779,6 +782,27 @@ __device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, i
     u = lane < nf ? s / lamn : 0.f;
     wave_sync();
     return true;
+}
+
+// Implicit feedback: the global Gram G = Y^T Y (row-major, stride NF, zero
+// outside n_f) and lambda on the diagonal; identity rows for lanes >= nf.
+__device__ __forceinline__ void finish_system_implicit(float (&A)[NF], float &rhs, const float *G, float lam,
+                                                       int lane, int nf) {
+    const int ol = opaque_lane(lane);
+    const bool pad = ol >= nf;
+    const float *g = G + (pad ? 0 : ol) * NF;
+#pragma unroll
+    for (int b4 = 0; b4 < NF / 4; ++b4) {
+        const float4 gv = *reinterpret_cast<const float4 *>(g + 4 * b4);
+        const float gg[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * b4 + q;
+            const float v = A[b] + gg[q] + ((b == ol) ? lam : 0.f);
+            A[b] = pad ? ((b == ol) ? 1.f : 0.f) : v;
+        }
+    }
+    if (pad) rhs = 0.f;
 }
 
 __device__ __forceinline__ float system_tol(const float (&A)[NF], int nf) {

@@ -46,7 +46,9 @@ __device__ __forceinline__ Cut select_for_class(LDS &L, RowCtx &r, int s, int la
 // FAST (fast variant): no per-row selection; every row, of any class, keeps
 // the entries its column's global cut (a.gT, a.gK) keeps, ties decided by
 // the row index in `other`.
-template <int CLS, bool CHECK, bool STRIDED, bool FAST = false>
+// IMPL (implicit feedback): the system G + X*^T W X + lambda E with W =
+// diag(alpha y), right-hand side X*^T (1 + alpha y), G = a.G.
+template <int CLS, bool CHECK, bool STRIDED, bool FAST = false, bool IMPL = false>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     // the two smallest classes solve in Woodbury form from one chunk of at
     // most WB_D rows: 32-row chunks, half the LDS per wavefront
@@ -109,7 +111,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                 return;
             }
         }
-        if constexpr (!CHECK && (FAST || CLS == CLS_NET1 || CLS == CLS_NET2)) {
+        if constexpr (!CHECK && !IMPL && (FAST || CLS == CLS_NET1 || CLS == CLS_NET2)) {
             // few entries: the n x n Woodbury form of the same system
             if (n <= WB_D && (FAST || s > 0) && a.lam > 0.f) {
                 stage(L, r, 0, lane);  // the whole row is chunk 0 (staged above)
@@ -129,9 +131,14 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
         // singular): the full-data update of eq. (U)
 #pragma unroll 1
         for (int attempt = 0; attempt < 2; ++attempt) {
-            if constexpr (kCore) gram_range_sparse(L, r, c, 0, n, lane, A, rhs);
-            else gram(L, r, c, lane, A, rhs);
-            finish_system(A, rhs, lamn, lane, a.nf);
+            if constexpr (IMPL) {
+                gram_range_sparse<LDS, true>(L, r, c, 0, n, lane, A, rhs, a.alpha);
+                finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
+            } else {
+                if constexpr (kCore) gram_range_sparse(L, r, c, 0, n, lane, A, rhs);
+                else gram(L, r, c, lane, A, rhs);
+                finish_system(A, rhs, lamn, lane, a.nf);
+            }
             const bool ok = solve<kCore>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
             if (ok) break;
             u = 0.f;
@@ -241,6 +248,13 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAV
 // light rows are contiguous in the row order).
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_fast(SweepArgs a) {
     sweep_rows<CLS_NET1, false, false, true>(a);
+}
+
+// Implicit-feedback Core-ALS, one kernel per degree class.
+template <int CLS>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_implicit(
+    SweepArgs a) {
+    sweep_rows<CLS, false, false, false, true>(a);
 }
 
 // Fold-in answers: residual check of the candidates, exact solve of the rest.
@@ -359,6 +373,26 @@ hipError_t launch_sweep_class(int cls, const SweepArgs &a, int max_blocks, hipSt
 hipError_t launch_check_class(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
     if (!a.guess || !a.path || !a.rho) return hipErrorInvalidValue;
     return launch_class<true>(cls, a, max_blocks, s);
+}
+
+hipError_t launch_sweep_implicit(int cls, const SweepArgs &a, int max_blocks, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    if (!a.G) return hipErrorInvalidValue;
+    int64_t blocks = (a.count + WPB - 1) / WPB;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    const dim3 g((unsigned)blocks), b(WPB * 64);
+    switch (cls) {
+        case CLS_FULL: hipLaunchKernelGGL(k_sweep_implicit<CLS_FULL>, g, b, 0, s, a); break;
+        case CLS_NET1: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET1>, g, b, 0, s, a); break;
+        case CLS_NET2: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET2>, g, b, 0, s, a); break;
+        case CLS_NET4: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET4>, g, b, 0, s, a); break;
+        case CLS_NET8: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET8>, g, b, 0, s, a); break;
+        case CLS_NET16: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET16>, g, b, 0, s, a); break;
+        case CLS_NET32: hipLaunchKernelGGL(k_sweep_implicit<CLS_NET32>, g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_fast(const SweepArgs &a, int max_blocks, hipStream_t s) {
