@@ -28,6 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32 instructions (the library is built
 # without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 78.6
+# confidence scale of the implicit-feedback variant (Hu, Koren and Volinsky
+# use 40 on counts; the synthetic ratings are of order 1)
+IMPLICIT_ALPHA = 40.0
 
 
 def log(msg):
@@ -89,18 +92,22 @@ def class_work(deg, num, den, min_keep, nf, heavy_n=1024):
     return out
 
 
-def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, precision=0, cfg=None, fast=False):
+def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, precision=0, cfg=None, fast=False,
+                 implicit_alpha=None):
     """Time `steps` sweeps (users + items half-sweep) after `warmup` untimed
     ones, on the context's own stream: once as eager launches with per-kernel
-    HIP events (the timed region), once as HIP-graph replays."""
+    HIP events (the timed region), once as HIP-graph replays.  implicit_alpha:
+    implicit-feedback Core-ALS with the ratings' magnitudes as confidences."""
     from paper_2509_18024_amd import capi
     from paper_2509_18024_amd.als import CoreALS
     cfg = cfg or {}
     rp, ci, v = gpu_csr
     t0 = time.time()
     with torch.cuda.stream(stream):
+        if implicit_alpha is not None:
+            v = torch.abs(v)
         als = CoreALS(prob.n_u, prob.n_m, prob.n_f, rp, ci, v, prob.lam, budget, prob.min_keep, precision,
-                      stream=stream, graphs=True, fast=fast, **cfg)
+                      stream=stream, graphs=True, fast=fast, implicit_alpha=implicit_alpha, **cfg)
         stream.synchronize()
         init_s = time.time() - t0
         counts = capi.als_class_counts(als.ctx)
@@ -135,12 +142,14 @@ def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, preci
         g1.record(stream)
         stream.synchronize()
         graph_ms = g0.elapsed_time(g1) / steps
-        obj = als.objective(U, M)
+        # the explicit loss; implicit feedback has a different one
+        obj = als.objective(U, M) if implicit_alpha is None else {"rmse": None, "remse": None, "f": None}
     ms = ms_total / steps
     res = {
         "budget": f"{budget[0]}/{budget[1]}",
         "precision": ["fp32", "bf16+ir(fp32 residual)", "bf16+ir(fp64 residual)", "auto"][precision],
-        "method": "fast variant (global sketch)" if fast else "per-row CES",
+        "method": ("fast variant (global sketch)" if fast else "per-row CES")
+        + ("" if implicit_alpha is None else f", implicit feedback (alpha {implicit_alpha}, confidences |r|)"),
         "schedule": cfg,
         "sweep_ms": ms,
         "sweep_s": ms / 1000.0,
@@ -159,7 +168,8 @@ def time_variant(torch, prob, gpu_csr, stream, budget, steps, warmup, tag, preci
     }
     log(f"{tag}: r={res['budget']} {res['precision']} sweep {ms:.3f} ms (graph replay {graph_ms:.3f}), "
         f"{res['solves_per_s']:.3e} solves/s, "
-        f"rmse {obj['rmse']:.5f} after {warmup + 2 * steps} it, init {init_s:.2f}s, schedule {cfg}")
+        f"rmse {obj['rmse'] if obj['rmse'] is None else round(obj['rmse'], 5)} after {warmup + 2 * steps} it, "
+        f"init {init_s:.2f}s, schedule {cfg}")
     return als, res, M
 
 
@@ -468,12 +478,13 @@ def main():
     # FP32 products on bf16 MFMA tiles); comparator: plain full-data ALS in FP32 on the same GPU
     from paper_2509_18024_amd import autotune
     HEAD = "core_r1/10_fp32"
-    variants = [(HEAD, (1, 10), 0, False)]
+    variants = [(HEAD, (1, 10), 0, "")]
     if not args.headline_only:
-        variants += [("core_r1/10_bf16ir", (1, 10), 1, False), ("core_r1/10_auto", (1, 10), 3, False),
-                     ("core_fast_r1/10_fp32", (1, 10), 0, True),
-                     ("core_r1/20_fp32", (1, 20), 0, False), ("core_r1/4_fp32", (1, 4), 0, False),
-                     ("full_fp32", (1, 1), 0, False), ("full_bf16ir", (1, 1), 1, False)]
+        variants += [("core_r1/10_bf16ir", (1, 10), 1, ""), ("core_r1/10_auto", (1, 10), 3, ""),
+                     ("core_fast_r1/10_fp32", (1, 10), 0, "fast"),
+                     ("core_implicit_r1/10_fp32", (1, 10), 0, "implicit"),
+                     ("core_r1/20_fp32", (1, 20), 0, ""), ("core_r1/4_fp32", (1, 4), 0, ""),
+                     ("full_fp32", (1, 1), 0, ""), ("full_bf16ir", (1, 1), 1, "")]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         gpu_csr = (torch.from_numpy(prob.row_ptr).to(dev), torch.from_numpy(prob.col_idx).to(dev),
@@ -499,10 +510,10 @@ def main():
             schedules[key] = autotune.tune(torch, prob, gpu_csr, b, prec, stream, log, path=tune_out)
     results = {}
     head_als = None
-    for tag, b, prec, fast in variants:
+    for tag, b, prec, mode in variants:
         cfg = schedules["full" if b[0] == b[1] else "core"]
         als, res, M_fin = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg,
-                                       fast)
+                                       mode == "fast", IMPLICIT_ALPHA if mode == "implicit" else None)
         results[tag] = res
         if tag == HEAD:
             head_als = als
@@ -608,8 +619,8 @@ def main():
         "core_vs_full": {k: {kk: v[kk] for kk in ("budget", "precision", "method", "sweep_s", "solves_per_s",
                                                    "rmse", "iterations_done")}
                          for k, v in results.items()},
-        "method_rmse_gap_vs_full": ({k: v["rmse"] - full["rmse"] for k, v in results.items()}
-                                    if full else None),
+        "method_rmse_gap_vs_full": ({k: v["rmse"] - full["rmse"] for k, v in results.items()
+                                     if v["rmse"] is not None} if full else None),
         "speedup_core_vs_full": ({k: full["sweep_s"] / v["sweep_s"] for k, v in results.items()}
                                  if full else None),
         "per_kernel": per_kernel,
