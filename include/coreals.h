@@ -163,6 +163,11 @@ typedef struct {
                                     |b - A u0| / |b| of a refined row's first
                                     solution u0 (A u = b its system); 0 when no
                                     row is refined                                */
+    int64_t n_select_hinted;     /* heavy rows whose selection found each column's
+                                    16-bit threshold in one counting pass over a
+                                    window around the same row's threshold of the
+                                    previous half-sweep of this side (the cuts are
+                                    exact either way)                             */
 } als_sweep_stats;
 
 typedef struct {

@@ -321,6 +321,8 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         h.cutT = H.cutT;
         h.cutK = H.cutK;
         h.cstride = c->wide ? NFW : 64;
+        // cutT still holds this side's cuts of its previous half-sweep
+        h.hint = c->wide ? 0 : 1;
         h.col_base = 0;
         h.flag = c->flag[side];
         h.pass = 0;
@@ -516,6 +518,7 @@ als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als
     double mr;
     std::memcpy(&mr, &h[ST_MAXRES], sizeof(mr));
     st->max_rel_residual = mr;
+    st->n_select_hinted = (int64_t)h[ST_HINTED];
     return ALS_OK;
 }
 
@@ -691,6 +694,8 @@ als_status als_init(const als_problem *p, als_ctx **out) {
         c->uK[sd] = L.side[sd].uK;
         if (H.n_heavy == 0) continue;
         if (H.n_heavy > heavy_bound(*p, S.n_rows)) return bail(ALS_E_STATE, "heavy-row bound violated");
+        // no previous cuts yet: the selection's first half-sweep takes no hint
+        INIT_HIP(hipMemsetAsync(H.cutT, 0xFF, sizeof(int32_t) * (size_t)H.n_heavy * cut_stride(*p), s));
         std::vector<int32_t> rows((size_t)H.n_heavy);
         std::vector<int64_t> ptr((size_t)S.n_rows + 1);
         INIT_HIP(hipMemcpyAsync(rows.data(), S.perm + S.class_off[CLS_HEAVY], sizeof(int32_t) * rows.size(),

@@ -13,7 +13,13 @@
 //                    into LDS and ranked exactly by (key desc, position asc);
 //                    only if more than HEAVY_CAP keys share it do two more
 //                    radix passes over the full keys run, and a position pass
-//                    where keys equal the threshold.
+//                    where keys equal the threshold.  When the row's cuts of
+//                    the previous half-sweep of this side are at hand, one
+//                    counting pass over a 256-bin window of 16-bit keys around
+//                    each previous threshold replaces the first two passes; it
+//                    is exact, because the counts above and inside the window
+//                    decide whether the new threshold lies inside (else the
+//                    two passes run as before).
 //   k_heavy_gram_x6  one wavefront per (row, chunk of `chunk` entries) builds
 //                    the chunk's part of X*^T X and X*^T y (eq. core_ui) with
 //                    the row's cut, FP32 products from an exact three-way
@@ -69,6 +75,7 @@ struct HeavySelLds {
     int done[64];
     int T[64];
     int K[64];
+    int wlo[64];  // hint pass: the window's lowest 16-bit key
     int flag;
 };
 
@@ -204,6 +211,50 @@ __device__ __forceinline__ void heavy_hist_pass(HeavySelLds &S, const int32_t *i
     });
 }
 
+// Hint pass: for keys whose 16-bit key k16 is at least the column's window
+// start wlo, count bin min(k16 - wlo, 255) (packed 16-bit counters, as in the
+// narrow passes); bin 255 gathers every key at or above wlo + 255.
+template <int KOFF, class RG>
+__device__ __forceinline__ void heavy_hint_pass(HeavySelLds &S, const int32_t *idx, const RG &R, int64_t beg, int n,
+                                                int w, int lane) {
+    const int wlo = S.wlo[lane];
+    for_chunks(idx, beg, n, w, lane, [&](int colv, int, int m) {
+        gather_chunk(R, colv, m, [&](int b, int) {
+            const int k16 = (int)__builtin_amdgcn_ubfe((unsigned)b, 15 - KOFF, 16);
+            const int d = min(k16 - wlo, 255);
+            if (d >= 0) atomicAdd(&S.hist[d >> 1][lane], (d & 1) ? 0x10000u : 1u);
+        });
+    });
+}
+
+// Column a after the hint pass: the rem-th largest key lies in bin d < 255
+// (a hit: its 16-bit key is wlo + d, as two narrow passes would have fixed
+// it) or outside the window (a miss: returns false).
+__device__ __forceinline__ bool heavy_pick_hint(HeavySelLds &S, int a) {
+    if (S.done[a]) return true;
+    const int rem = S.rem[a];
+    int cum = 0, dsel = -1, hsel = 0;
+    for (int d = 255; d >= 0; --d) {
+        const int h = (int)((S.hist[d >> 1][a] >> ((d & 1) << 4)) & 0xFFFFu);
+        if (cum + h >= rem) {
+            dsel = d;
+            hsel = h;
+            break;
+        }
+        cum += h;
+    }
+    if (dsel < 0 || dsel == 255) return false;
+    S.rem[a] = rem - cum;
+    S.prefix[a] = (S.wlo[a] + dsel) << 15;
+    S.ceq[a] = hsel;
+    if (hsel == S.rem[a]) {  // every key with this prefix is kept
+        S.done[a] = 1;
+        S.T[a] = S.prefix[a];
+        S.K[a] = 0x7FFFFFFF;
+    }
+    return true;
+}
+
 // Column a: walk digits dhi-1 .. dlo from the top; if the rem-th largest key
 // falls in this range, fix the digit, else carry the running count.
 __device__ __forceinline__ void heavy_pick(HeavySelLds &S, int a, int shift, int dlo, int dhi, bool wide) {
@@ -285,7 +336,56 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         }
         int hmask = 0;
         bool collected = false, all_done = false;
-        for (int pass = 0; pass < 4; ++pass) {
+        int pass0 = 0;
+        if (a.hint && !wide) {
+            // the previous cuts of this row, where every live column has one
+            if (tid == 0) S.flag = 0;
+            __syncthreads();
+            if (tid < 64) {
+                const int h = a.cutT[t * a.cstride + a.col_base + tid];
+                const int p16 = max(0, h) >> 15;
+                S.wlo[tid] = min(max(p16 - 127, 0), 65535 - 254);
+                if (!S.done[tid] && h < 0) atomicOr(&S.flag, 1);
+            }
+            for (int q = tid; q < 128 * 64; q += HS_THREADS) (&S.hist[0][0])[q] = 0u;
+            __syncthreads();
+            if (!S.flag) {
+                if (K16)
+                    heavy_hint_pass<15>(S, a.idx, R16, beg, n, w, lane);
+                else
+                    heavy_hint_pass<0>(S, a.idx, R, beg, n, w, lane);
+                __syncthreads();
+                if (tid < 64 && !heavy_pick_hint(S, tid)) atomicOr(&S.flag, 4);
+                __syncthreads();
+                if (S.flag & 4) {
+                    // some threshold left its window: the two first passes
+                    if (tid < 64) {
+                        const bool pad = a.col_base + tid >= nf;
+                        S.prefix[tid] = 0;
+                        S.rem[tid] = s;
+                        S.done[tid] = pad ? 1 : 0;
+                        S.T[tid] = 0;
+                        S.K[tid] = pad ? s - 1 : 0x7FFFFFFF;
+                    }
+                } else {
+                    if (tid == 0) S.flag = 0;
+                    __syncthreads();
+                    if (tid < 64 && !S.done[tid]) {
+                        atomicOr(&S.flag, 2);
+                        if (S.ceq[tid] > HEAVY_CAP) atomicOr(&S.flag, 1);
+                    }
+                    __syncthreads();
+                    const int f = S.flag;
+                    hmask = 0xFFFF << 15;
+                    pass0 = 2;
+                    if (tid == 0) atomicAdd(&a.stats[ST_HINTED], 1ull);
+                    if (!(f & 2)) all_done = true;
+                    else if (!(f & 1)) collected = true;
+                }
+            }
+            __syncthreads();
+        }
+        for (int pass = pass0; pass < 4 && !all_done && !collected; ++pass) {
             const int shift = pass < 3 ? 23 - 8 * pass : 0;
             const int width = pass < 3 ? 8 : 7;
             const int nd = 1 << width;

@@ -132,6 +132,7 @@ enum StatSlot : int {
     ST_FOLDIN_EXACT = 4,
     ST_FP32GRAM = 5,
     ST_MAXRES = 6,  // bits of the largest relative refinement residual (non-negative double)
+    ST_HINTED = 7,  // heavy rows whose selection started from the previous cuts
     NSTATS = 8
 };
 
@@ -184,6 +185,7 @@ struct HeavyArgs {
     const int32_t *pair_chunk;
     const int64_t *pair_off;
     int32_t *cutT;            // [heavy slot * cstride + column]
+    int32_t hint;             // selection: cutT holds this side's previous cuts (-1 where none)
     int32_t *cutK;
     int32_t cstride;          // cut entries per row: 64, or NFW at ranks above 64
     int32_t col_base;         // selection: the launch ranks columns col_base .. + 63
