@@ -348,22 +348,25 @@ __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &
         uint64_t bits = 0;
         for (int k = 0; k < m; ++k)
             if (kept(c, key_of(L.X[k][lane]), tie_pos(L, k0, k))) bits |= 1ull << k;
-        while (__ballot(bits != 0ull)) {
-            if (bits != 0ull) {
-                const int k = __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1;
-                const float xk = L.X[k][lane];
-                const float w = WEIGHTED ? xk * (alpha * L.y[k]) : xk;
+        // uniform loop, one kept entry per lane per trip: lanes with none
+        // left add zero times staged row 0 (a branch here would make the
+        // compiler copy all 64 accumulators at every trip)
+        for (;;) {
+            const bool has = bits != 0ull;
+            if (__ballot(has) == 0ull) break;
+            const int k = has ? __ffsll((unsigned long long)bits) - 1 : 0;
+            bits &= bits - 1;
+            const float xk = has ? L.X[k][lane] : 0.f;
+            const float w = WEIGHTED ? xk * (alpha * L.y[k]) : xk;
 #pragma unroll
-                for (int b4 = 0; b4 < NF / 4; ++b4) {
-                    const float4 xr = *reinterpret_cast<const float4 *>(&L.X[k][b4 * 4]);
-                    A[4 * b4 + 0] = fmaf(w, xr.x, A[4 * b4 + 0]);
-                    A[4 * b4 + 1] = fmaf(w, xr.y, A[4 * b4 + 1]);
-                    A[4 * b4 + 2] = fmaf(w, xr.z, A[4 * b4 + 2]);
-                    A[4 * b4 + 3] = fmaf(w, xr.w, A[4 * b4 + 3]);
-                }
-                rhs = WEIGHTED ? fmaf(xk, fmaf(alpha, L.y[k], 1.f), rhs) : fmaf(w, L.y[k], rhs);
+            for (int b4 = 0; b4 < NF / 4; ++b4) {
+                const float4 xr = *reinterpret_cast<const float4 *>(&L.X[k][b4 * 4]);
+                A[4 * b4 + 0] = fmaf(w, xr.x, A[4 * b4 + 0]);
+                A[4 * b4 + 1] = fmaf(w, xr.y, A[4 * b4 + 1]);
+                A[4 * b4 + 2] = fmaf(w, xr.z, A[4 * b4 + 2]);
+                A[4 * b4 + 3] = fmaf(w, xr.w, A[4 * b4 + 3]);
             }
+            rhs = WEIGHTED ? fmaf(xk, fmaf(alpha, L.y[k], 1.f), rhs) : fmaf(w, L.y[k], rhs);
         }
     }
 }
