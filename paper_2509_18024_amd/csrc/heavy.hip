@@ -616,7 +616,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
             const float anorm = __int_as_float(wave_max_key(__float_as_int(rs)));
             int my_step;
             float r[1] = {rhs};
-            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step);
+            ok = lu_keep(A, r, lane, a.nf, system_tol(A, a.nf), my_step, L);
             int need64 = 0;        // bit 16 of the kept step: FP64 residual for this row
             bool regram = false;   // ALS_PREC_AUTO: Gram again with FP32 products
             if (ok) {
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
                 if (regram) atomicAdd(&a.stats[ST_FP32GRAM], 1ull);
             }
         } else {
-            ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            ok = solve<true, WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
         }
         if (!ok) {
             u = 0.f;
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
                     gram(L, r, full, lane, A, rhs);
                     finish_system(A, rhs, lamn, lane, a.nf);
                 }
-                ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+                ok = solve<true, WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
                 if (!ok) u = 0.f;
             }
         }

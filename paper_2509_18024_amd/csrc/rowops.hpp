@@ -56,6 +56,9 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 // halves the LDS per wavefront.
 // COLS (fast variant): the staged rows' indices into `other` are kept too,
 // and ties of the cut are decided by them instead of the positions.
+// Columns per panel of the blocked elimination.
+constexpr int LU_BLK = 4;
+
 template <int ROWS, bool COLS = false>
 struct alignas(16) WaveLdsT {
     static constexpr int rows = ROWS;
@@ -64,6 +67,7 @@ struct alignas(16) WaveLdsT {
     float y[ROWS];
     float urhs[2 * NF];       // solve: solution components parked by the back substitution
     double rres[ROWS];        // refinement: residuals y_k - x_k . u of the staged rows
+    float pbuf[LU_BLK][NF];   // blocked elimination: the panel's pivot rows
     int col[COLS ? ROWS : 1]; // indices of the staged rows into `other`
 };
 using WaveLds = WaveLdsT<CK>;
@@ -505,6 +509,94 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     for (int q = 0; q < NR; ++q) rhs[q] = fmaf(-l, readlane_f(rhs[q], p), rhs[q]);
 }
 
+// Blocked elimination (panels of LU_BLK columns).  Step J eliminates column J
+// exactly as elim_step_u, but updates only the panel's later columns at once;
+// the columns after the panel wait for the panel's end, where every row
+// subtracts one combination of the panel's pivot rows (their values at the
+// panel's start, broadcast through LDS instead of one v_readlane per entry).
+// With l_j the row's multiplier at panel step j and p_j that step's pivot row,
+// the row's total update of a later column c is
+//     sum_j l_j U_j[c],  U_j = A_{p_j} - sum_{i<j} l_i(p_j) U_i,
+// = sum_j l'_j A_{p_j}[c] with l' solving the unit upper triangular system
+// l'_i = l_i - sum_{j>i} l_i(p_j) l'_j (the panel's own multipliers).
+template <bool PIVOT, int NR, int J, bool KEEP>
+__device__ __forceinline__ void blk_step(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
+                                         int &my_step, bool &ok, int &pk, float (&lp)[LU_BLK], int (&pv)[LU_BLK],
+                                         float (*pb)[NF]) {
+    constexpr int JJ = J % LU_BLK;
+    constexpr int P0 = J - JJ;
+    constexpr int PE = P0 + LU_BLK;  // first column after the panel
+    int p;
+    bool active;
+    if constexpr (PIVOT) {
+        active = my_step == NF;
+        p = 63 - (pk & 63);
+    } else {
+        active = lane >= J;
+        p = J;
+    }
+    const float piv = readlane_f(A[J], p);
+    ok = ok && (J >= nf || fabsf(piv) > tol);
+    const bool elim = active && lane != p;
+    const float l = elim ? A[J] * __builtin_amdgcn_rcpf(piv) : 0.f;
+    if constexpr (KEEP) A[J] = elim ? l : A[J];
+    if (lane == p) my_step = J;
+    lp[JJ] = l;
+    pv[JJ] = p;
+    // the panel's later columns now
+#pragma unroll
+    for (int c = J + 1; c < PE; ++c) {
+        A[c] = fmaf(-l, readlane_f(A[c], p), A[c]);
+        if constexpr (PIVOT)
+            if (c == J + 1) pk = pivot_key<J + 1>(A, lane, my_step);  // column J + 1 is final
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) rhs[q] = fmaf(-l, readlane_f(rhs[q], p), rhs[q]);
+    if constexpr (JJ == LU_BLK - 1 && PE < NF) {
+        // panel end: the rows' combined update of columns PE .. NF - 1
+        float lt[LU_BLK];
+#pragma unroll
+        for (int i = LU_BLK - 1; i >= 0; --i) {
+            lt[i] = lp[i];
+#pragma unroll
+            for (int j = i + 1; j < LU_BLK; ++j) lt[i] = fmaf(-readlane_f(lp[i], pv[j]), lt[j], lt[i]);
+        }
+        int slot = -1;
+#pragma unroll
+        for (int j = 0; j < LU_BLK; ++j)
+            if (lane == pv[j]) slot = j;
+        wave_sync();
+        if (slot >= 0) {
+#pragma unroll
+            for (int c = PE; c < NF; c += 4)
+                *reinterpret_cast<float4 *>(&pb[slot][c]) = make_float4(A[c], A[c + 1], A[c + 2], A[c + 3]);
+        }
+        wave_sync();
+#pragma unroll
+        for (int c = PE; c < NF; c += 4) {
+#pragma unroll
+            for (int j = 0; j < LU_BLK; ++j) {
+                const float4 v = *reinterpret_cast<const float4 *>(&pb[j][c]);
+                A[c + 0] = fmaf(-lt[j], v.x, A[c + 0]);
+                A[c + 1] = fmaf(-lt[j], v.y, A[c + 1]);
+                A[c + 2] = fmaf(-lt[j], v.z, A[c + 2]);
+                A[c + 3] = fmaf(-lt[j], v.w, A[c + 3]);
+            }
+            if constexpr (PIVOT)
+                if (c == PE) pk = pivot_key<PE>(A, lane, my_step);  // column PE is final
+        }
+    }
+}
+
+template <bool PIVOT, int NR, bool KEEP, int... J>
+__device__ __forceinline__ void blk_all(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR], int lane,
+                                        int nf, float tol, int &my_step, bool &ok, float (*pb)[NF]) {
+    int pk = PIVOT ? pivot_key<0>(A, lane, my_step) : 0;
+    float lp[LU_BLK];
+    int pv[LU_BLK];
+    (blk_step<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok, pk, lp, pv, pb), ...);
+}
+
 template <bool PIVOT, int NR, int J>
 __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[NR], int lane, int my_step,
                                             float *xs) {
@@ -566,12 +658,18 @@ __device__ __forceinline__ void back_all_u(std::integer_sequence<int, J...>, con
 // Solve the register-resident system for NR right-hand sides at once; returns
 // false when a pivot of the first nf steps is <= tol.  On success x[q] holds
 // component `lane` of the solution for right-hand side q.
-template <bool PIVOT, int NR, class LDS>
+// BLOCKED: panels with LDS-broadcast updates (measured faster in the heavy-row
+// solve, which has the LDS to itself; the light-row kernels, whose Gram is
+// bound by LDS reads, keep the per-step broadcasts).
+template <bool PIVOT, int NR, class LDS, bool BLOCKED = false>
 __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
                                         float (&x)[NR], LDS &L) {
     int my_step = NF;  // elimination step at which this lane's row was the pivot
     bool ok = true;
-    elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    if constexpr (BLOCKED)
+        blk_all<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok, L.pbuf);
+    else
+        elim_all_u<PIVOT, NR, false>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
     if (!PIVOT) my_step = lane;
     if (!ok) return false;
     wave_sync();
@@ -583,12 +681,12 @@ __device__ __forceinline__ bool solve_n(float (&A)[NF], float (&rhs)[NR], int la
     return true;
 }
 
-template <bool PIVOT, class LDS>
+template <bool PIVOT, class LDS, bool BLOCKED = false>
 __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
                                       LDS &L) {
     float r[1] = {rhs};
     float x[1];
-    const bool ok = solve_n<PIVOT, 1>(A, r, lane, nf, tol, x, L);
+    const bool ok = solve_n<PIVOT, 1, LDS, BLOCKED>(A, r, lane, nf, tol, x, L);
     if (ok) u = x[0];
     return ok;
 }
@@ -596,10 +694,13 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
 // Pivoted LU that keeps its factors in A (multipliers below, U above the
 // pivots) and the lane's pivot step in my_step; returns false on a pivot of
 // the first nf steps <= tol.
-__device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lane, int nf, float tol, int &my_step) {
+// Blocked (heavy-row solve).
+template <class LDS>
+__device__ __forceinline__ bool lu_keep(float (&A)[NF], float (&rhs)[1], int lane, int nf, float tol, int &my_step,
+                                        LDS &L) {
     my_step = NF;
     bool ok = true;
-    elim_all_u<true, 1, true>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok);
+    blk_all<true, 1, true>(std::make_integer_sequence<int, NF>{}, A, rhs, lane, nf, tol, my_step, ok, L.pbuf);
     return ok;
 }
 
