@@ -29,10 +29,11 @@
 //                    order (deterministic), adds lambda n_i, and solves it
 //                    (pivoted LU).
 //
-// BF16 precision modes replace k_heavy_gram_x6 by k_heavy_gram_bf16 (the same
-// partial systems from plain bf16 roundings of the operands, FP32 accumulation) and add one
-// step of iterative refinement: k_heavy_resid forms the partial residuals
-// X*^T (y - X u) of each chunk in FP32 or FP64 from the fp32 data, and a
+// BF16 precision modes run k_heavy_gram_x6 with one product per tile (the
+// operands' bf16 roundings, FP32 accumulation) and add one step of iterative
+// refinement: k_heavy_resid forms the partial residuals X*^T (y - X u) of
+// each chunk in FP32 or FP64 from the fp32 data (the next 64 rows' gathers in
+// flight while a block is reduced), and a
 // second k_heavy_solve subtracts lambda n_i u, solves A d = rho with the LU
 // factors the first solve kept (in the row's first partial slot) and returns
 // u + d.
@@ -712,90 +713,6 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_refine(HeavyArgs a, int64_t 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-// Partial system of one (row, chunk) pair from bf16 MFMA tiles.  The 64x64
-// block X*^T X is four 32x32 tiles (a-half, b-half); each 16-position slab of
-// the staged rows feeds v_mfma_f32_32x32x16_bf16 with A = W^T (W = kept
-// entries of X, lane m of half h holds column 32t+m, positions 8h..8h+7) and
-// B = X (same positions, column 32t+m).  Output lane l holds column l%32 of a
-// tile and rows 8(r/4) + 4(l/32) + r%4 in accumulator r.
-__global__ __launch_bounds__(WPB * 64) void k_heavy_gram_bf16(HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
-    __shared__ WaveLds lds[WPB];
-    const int w = wave_index();
-    const int lane = threadIdx.x & 63;
-    const int m = lane & 31, h = lane >> 5;
-    WaveLds &L = lds[w];
-    const bool vec4 = (a.nf == NF) && ((reinterpret_cast<uintptr_t>(a.other) & 15) == 0);
-    for (int64_t p = pair_begin + (int64_t)blockIdx.x * WPB + w; p < pair_end; p += (int64_t)gridDim.x * WPB) {
-        const int64_t slot = a.pair_slot[p];
-        const int chunk = a.pair_chunk[p];
-        const int64_t i = a.rows[slot];
-        if (a.path && a.path[i] == 0) continue;  // fold-in answer accepted
-        const int64_t beg = a.ptr[i];
-        const int n = (int)(a.ptr[i + 1] - beg);
-        const int s = (int)budget_of(n, a.num, a.den, a.min_keep);
-        RowCtx r{a.idx, a.val, a.other, beg, n, a.nf, vec4, -1};
-        Cut c[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int col = 32 * t + m;
-            if (s == n) c[t] = Cut{0, 0, false, true};
-            else if (s == 0) c[t] = Cut{0, 0, true, false};
-            else c[t] = Cut{a.cutT[slot * 64 + col], a.cutK[slot * 64 + col], false, false};
-        }
-        f32x16 acc[2][2];
-#pragma unroll
-        for (int ta = 0; ta < 2; ++ta)
-#pragma unroll
-            for (int tb = 0; tb < 2; ++tb)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) acc[ta][tb][q] = 0.f;
-        float racc[2] = {0.f, 0.f};
-        const int kb = chunk * a.chunk;
-        const int ke = min(n, kb + a.chunk);
-        for (int k0 = kb; k0 < ke; k0 += CK) {
-            stage(L, r, k0, lane);
-            const int mrows = min(CK, ke - k0);
-            for (int s16 = 0; s16 < mrows; s16 += 16) {
-                bf16x8 av[2], bv[2];
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int col = 32 * t + m;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int kk = s16 + 8 * h + e;
-                        const float x = kk < mrows ? L.X[kk][col] : 0.f;
-                        const float wv = kept(c[t], key_of(x), k0 + kk) ? x : 0.f;
-                        av[t][e] = (__bf16)wv;
-                        bv[t][e] = (__bf16)x;
-                        racc[t] = fmaf(wv, L.y[kk], racc[t]);
-                    }
-                }
-#pragma unroll
-                for (int ta = 0; ta < 2; ++ta)
-#pragma unroll
-                    for (int tb = 0; tb < 2; ++tb)
-                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ta], bv[tb], acc[ta][tb], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t) racc[t] += __shfl_xor(racc[t], 32);
-        float *dst = a.partials + (p - pair_begin) * (int64_t)(NF + 1) * 64;
-#pragma unroll
-        for (int ta = 0; ta < 2; ++ta)
-#pragma unroll
-            for (int tb = 0; tb < 2; ++tb)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int row = 8 * (q >> 2) + 4 * h + (q & 3);
-                    dst[(32 * tb + m) * 64 + 32 * ta + row] = acc[ta][tb][q];
-                }
-        if (h == 0) {
-            dst[NF * 64 + m] = racc[0];
-            dst[NF * 64 + 32 + m] = racc[1];
-        }
-    }
-}
-
 constexpr uint32_t GF_NONE = 0x80000000u;  // a buffer offset past any factor matrix
 
 // Partial system of a (row, chunk) pair, A = X*^T X and b = X*^T y over the
@@ -838,7 +755,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 // the right-hand side), every remaining entry kept.
 // IMPL (implicit feedback): the kept operand is weighted by alpha y_k and the
 // right-hand side sums x_ka (1 + alpha y_k).
-template <bool BUF, bool GPOS, bool UNIF, bool IMPL = false>
+// ONE (BF16 precision modes): the products of the operands' bf16 roundings
+// only, one MFMA per tile; a refinement step follows.
+template <bool BUF, bool GPOS, bool UNIF, bool IMPL = false, bool ONE = false>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_heavy_gram_x6(
     HeavyArgs a, int64_t pair_begin, int64_t pair_end) {
     __shared__ int s_col[WPB][64];
@@ -1024,12 +943,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3, 3))
 #define GX_MFMA(A, B)                                                                             \
     _Pragma("unroll") for (int ta = 0; ta < 2; ++ta) _Pragma("unroll") for (int tb = 0; tb < 2; ++tb) \
         acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[ta], B[tb], acc[ta][tb], 0, 0, 0);
-                    GX_MFMA(al, bh)
-                    GX_MFMA(ah, bl)
-                    GX_MFMA(am, bm)
-                    GX_MFMA(am, bh)
-                    GX_MFMA(ah, bm)
-                    GX_MFMA(ah, bh)
+                    if constexpr (ONE) {
+                        GX_MFMA(ah, bh)
+                    } else {
+                        GX_MFMA(al, bh)
+                        GX_MFMA(ah, bl)
+                        GX_MFMA(am, bm)
+                        GX_MFMA(am, bh)
+                        GX_MFMA(ah, bm)
+                        GX_MFMA(ah, bh)
+                    }
 #undef GX_MFMA
                 }
             }
@@ -1066,9 +989,55 @@ __device__ __forceinline__ void heavy_resid_pair(const HeavyArgs &a, WaveLds &L,
     double bs = 0.0;  // the chunk's share of b = X*^T y
     const int kb = chunk * a.chunk;
     const int ke = min(n, kb + a.chunk);
+    // 64-row blocks: with float4 rows, the next block's gathers are in flight
+    // while this one is reduced, and the indices of the one after
+    const bool pipe = r.vec4;
+    int colA = 0;
+    float yA = 0.f;
+    float4 v[CK / 4];
+    auto load_idx = [&](int k0, int &col, float &yv) {
+        col = 0;
+        yv = 0.f;
+        if (k0 + lane < ke) {
+            col = r.idx[r.beg + k0 + lane];
+            yv = r.val[r.beg + k0 + lane];
+        }
+    };
+    // gathers of the block whose indices lane j holds (row j of the block)
+    auto gather = [&](int col) {
+#pragma unroll
+        for (int t = 0; t < CK / 4; ++t) {
+            const int c = __shfl(col, t * 4 + (lane >> 4));
+            v[t] = *reinterpret_cast<const float4 *>(r.other + (size_t)c * NF + (lane & 15) * 4);
+        }
+    };
+    float ycur = 0.f;
+    if (pipe) {
+        int c0;
+        load_idx(kb, c0, ycur);
+        gather(c0);
+        load_idx(kb + CK, colA, yA);
+    }
     for (int k0 = kb; k0 < ke; k0 += CK) {
-        stage(L, r, k0, lane);
         const int mrows = min(CK, ke - k0);
+        if (pipe) {
+            wave_sync();
+            L.y[lane] = ycur;
+#pragma unroll
+            for (int t = 0; t < CK / 4; ++t) {
+                const int kk = t * 4 + (lane >> 4);
+                *reinterpret_cast<float4 *>(&L.X[kk][(lane & 15) * 4]) =
+                    kk < mrows ? v[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            wave_sync();
+            ycur = yA;
+            if (k0 + CK < ke) {
+                gather(colA);
+                load_idx(k0 + 2 * CK, colA, yA);
+            }
+        } else {
+            stage(L, r, k0, lane);
+        }
         acc_t rk = 0;
         if (lane < mrows) {
             acc_t dot = 0;
@@ -1084,12 +1053,14 @@ __device__ __forceinline__ void heavy_resid_pair(const HeavyArgs &a, WaveLds &L,
         }
         L.rres[lane] = (double)rk;
         wave_sync();
-        for (int kk = 0; kk < mrows; ++kk) {
+        // all CK rows, unrolled and without branches (unkept and past-the-end
+        // rows add zero), so that the LDS reads of a batch are in flight together
+#pragma unroll 16
+        for (int kk = 0; kk < CK; ++kk) {
             const float x = L.X[kk][lane];
-            if (kept(c, key_of(x), k0 + kk)) {
-                acc += (acc_t)x * (acc_t)L.rres[kk];
-                bs += (double)x * (double)L.y[kk];
-            }
+            const float xm = (kk < mrows && kept(c, key_of(x), k0 + kk)) ? x : 0.f;
+            acc += (acc_t)xm * (acc_t)L.rres[kk];
+            bs += (double)xm * (double)L.y[kk];
         }
         wave_sync();
     }
@@ -1201,8 +1172,15 @@ unsigned blocks_for(int64_t items, int per_block, int64_t cap) {
 
 hipError_t launch_heavy_gram_bf16(const HeavyArgs &a, int64_t pair_begin, int64_t pair_end, hipStream_t s) {
     if (pair_end <= pair_begin) return hipSuccess;
-    hipLaunchKernelGGL(k_heavy_gram_bf16, dim3(blocks_for(pair_end - pair_begin, WPB, 65536)), dim3(WPB * 64), 0, s,
-                       a, pair_begin, pair_end);
+    const bool buf = a.other_rows > 0 && a.other_rows < (1 << 24) &&
+                     a.other_rows * (int64_t)a.nf * 4 <= (int64_t)0x7FFFFFFF;
+    const dim3 grid(blocks_for(pair_end - pair_begin, WPB, 65536));
+    if (buf)
+        hipLaunchKernelGGL((k_heavy_gram_x6<true, false, false, false, true>), grid, dim3(WPB * 64), 0, s, a,
+                           pair_begin, pair_end);
+    else
+        hipLaunchKernelGGL((k_heavy_gram_x6<false, false, false, false, true>), grid, dim3(WPB * 64), 0, s, a,
+                           pair_begin, pair_end);
     return hipGetLastError();
 }
 

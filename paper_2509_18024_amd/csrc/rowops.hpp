@@ -403,12 +403,14 @@ __device__ __forceinline__ void resid_range(LDS &L, RowCtx &r, const Cut &c, int
         }
         if (lane < LDS::rows) L.rres[lane] = (double)rk;
         wave_sync();
-        for (int k = 0; k < m; ++k) {
+        // every staged row, unrolled and without branches (unkept and
+        // past-the-end rows add zero): the LDS reads of a batch overlap
+#pragma unroll 16
+        for (int k = 0; k < LDS::rows; ++k) {
             const float x = L.X[k][lane];
-            if (kept(c, key_of(x), k0 + k)) {
-                rho += (double)x * L.rres[k];
-                bsum += (double)x * (double)L.y[k];
-            }
+            const float xm = (k < m && kept(c, key_of(x), tie_pos(L, k0, k))) ? x : 0.f;
+            rho += (double)xm * L.rres[k];
+            bsum += (double)xm * (double)L.y[k];
         }
         wave_sync();
     }
