@@ -499,28 +499,32 @@ def main():
         gpu_csr = (torch.from_numpy(prob.row_ptr).to(dev), torch.from_numpy(prob.col_idx).to(dev),
                    torch.from_numpy(prob.val).to(dev))
     stream.synchronize()
-    # schedules: the committed tuning cache when it knows this problem, else a
-    # coordinate search on the box (written to gpurun_out/ for review)
+    # schedules, one per (budget, precision): the committed tuning cache when
+    # it knows this problem, else a coordinate search on the box (written to
+    # gpurun_out/ for review); the fast and implicit variants take the
+    # per-row method's schedule of their budget
     tune_out = os.path.join(ROOT, "gpurun_out", "tuning_gfx950.json")
     schedules = {}
-    for key, b, prec in [("core", (1, 10), 0), ("full", (1, 1), 0)]:
+    sig = autotune.degree_signature(prob.row_ptr, prob.col_idx, prob.n_m)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    for _, b, prec, _ in variants:
+        if (b, prec) in schedules:
+            continue
         if args.no_tune:
-            schedules[key] = dict(autotune.DEFAULT)
+            schedules[(b, prec)] = dict(autotune.DEFAULT)
             continue
         cached = autotune.load_cache()
-        sig = autotune.degree_signature(prob.row_ptr, prob.col_idx, prob.n_m)
-        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
         ck = autotune.cache_key(arch, prob.n_f, prec, b, sig, prob.nnz)
         if ck in cached:
-            schedules[key] = dict(cached[ck]["config"])
-            log(f"schedule {key}: tuning cache {schedules[key]}")
+            schedules[(b, prec)] = dict(cached[ck]["config"])
+            log(f"schedule r={b[0]}/{b[1]} precision {prec}: tuning cache {schedules[(b, prec)]}")
         else:
             os.makedirs(os.path.dirname(tune_out), exist_ok=True)
-            schedules[key] = autotune.tune(torch, prob, gpu_csr, b, prec, stream, log, path=tune_out)
+            schedules[(b, prec)] = autotune.tune(torch, prob, gpu_csr, b, prec, stream, log, path=tune_out)
     results = {}
     head_als = None
     for tag, b, prec, mode in variants:
-        cfg = schedules["full" if b[0] == b[1] else "core"]
+        cfg = schedules[(b, prec)]
         als, res, M_fin = time_variant(torch, prob, gpu_csr, stream, b, args.steps, args.warmup, tag, prec, cfg,
                                        mode == "fast", IMPLICIT_ALPHA if mode == "implicit" else None)
         results[tag] = res
