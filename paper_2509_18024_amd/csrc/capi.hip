@@ -46,6 +46,7 @@ struct Layout {
     float *partials;
     double *resid;
     uint16_t *key16;
+    int32_t *fb_rows;      // rows the Woodbury classes leave to the n_f x n_f solve
     double *gram_part;     // implicit: per-block partial Grams
     float *G;              // implicit: the Gram of the other factor matrix
     void *gsel;            // fast variant: radix-select state
@@ -127,6 +128,7 @@ Layout carve(const als_problem &p, void *base) {
     const bool impl = (p.flags & ALS_IMPLICIT) != 0;
     L.gram_part = c.take<double>(impl ? (size_t)implicit_gram_blocks() * NF * NF : 0);
     L.G = c.take<float>(impl ? (size_t)NF * NF : 0);
+    L.fb_rows = c.take<int32_t>((size_t)std::max(p.n_u, uo ? (int64_t)0 : p.n_m));
     L.gT = c.take<int32_t>(64);
     L.gK = c.take<int32_t>(64);
     for (int sd = 0; sd < 2; ++sd) {
@@ -281,6 +283,10 @@ als_status enqueue_half_sweep(als_ctx *c, int side, const float *other, float *o
         a.min_keep = c->p.min_keep;
         a.stats = sc.stats;
         a.queue = queues + cls;
+        // queue slots 9 .. 12: the Woodbury classes' fallback counts and queues
+        a.fb_rows = c->fb_rows;
+        a.fb_count = queues + 9 + (cls == CLS_NET2 ? 1 : 0);
+        a.fb_queue = queues + 11 + (cls == CLS_NET2 ? 1 : 0);
         a.guess = chk ? chk->guess : nullptr;
         a.tol = chk ? chk->tol : 0.f;
         a.path = chk ? chk->path : nullptr;
@@ -587,6 +593,7 @@ als_status als_init(const als_problem *p, als_ctx **out) {
     c->fast = (p->flags & ALS_FAST_VARIANT) != 0;
     c->unif = (p->flags & ALS_UNIF) != 0;
     c->implicit = (p->flags & ALS_IMPLICIT) != 0;
+    c->fb_rows = L.fb_rows;
     c->gram_part = L.gram_part;
     c->G = L.G;
     c->key16 = p->budget_num < p->budget_den && !c->fast && !c->unif ? L.key16 : nullptr;

@@ -163,6 +163,13 @@ struct SweepArgs {
     // implicit feedback: confidence weight and the Gram of `other` (NF x NF)
     float alpha;
     const float *G;
+    // Woodbury classes: rows the n x n form does not solve are listed here
+    // (fb_rows[0 .. *fb_count)) and solved by a second launch, whose row
+    // count is *count_dev (nullptr: count)
+    int32_t *fb_rows;
+    unsigned int *fb_count;
+    unsigned int *fb_queue;
+    const unsigned int *count_dev;
 };
 
 struct HeavyArgs {
@@ -338,6 +345,7 @@ struct als_ctx {
     bool fast = false;     // ALS_FAST_VARIANT: one global sketch per half-sweep
     bool unif = false;     // ALS_UNIF: uniform subsampling (the comparator)
     bool implicit = false; // ALS_IMPLICIT: implicit-feedback Core-ALS
+    int32_t *fb_rows = nullptr;   // rows the Woodbury classes leave to the n_f x n_f solve
     double *gram_part = nullptr;  // implicit: per-block partial Grams
     float *G = nullptr;           // implicit: the Gram of the other factor matrix
     uint64_t seed = 0;     // UNIF draws (als_set_sample_seed)

@@ -794,74 +794,71 @@ __device__ __forceinline__ bool wb_lu(std::integer_sequence<int, J...>, float (&
 }
 
 // Woodbury solve of a staged light row (n <= WB_D rows of X in L.X, cut c of
-// the lane's column).  Returns false, leaving L.X untouched, when the guard
-// fails; returns false after masking L.X in place when G is singular (the
-// caller re-stages).  On success u is component `lane` of the solution.
+// the lane's column).  Returns false when the guard fails or G is singular
+// (L.X is never modified: the caller's staged chunk stays valid).  On success
+// u is component `lane` of the solution.
+// W has s_i nonzeros per column, so G = lambda n E + X W^T is formed from the
+// kept (row, column) pairs only: G[k][l] sums x_ka x_la over the columns a
+// that keep row l, found from one ballot of the columns' kept masks per row.
 template <class LDS>
 __device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, int n, int nf, float lam,
                                                float lamn, bool &masked, float &u) {
     masked = false;
     static_assert(LDS::rows >= WB_D, "the Woodbury form stages the whole row");
-    // lane k holds design row k (rows n.. are the staged zero padding; lanes
-    // past the staged rows hold zeros)
-    float xk[NF];
-    float nrm = 0.f;
+    static_assert(WB_D <= 32, "kept masks are 32-bit");
+    // lane k < rows: design row k (rows n.. are the staged zero padding);
+    // lanes past the staged rows see zeros
     const int kr = min(lane, LDS::rows - 1);
-    const float lv = lane < LDS::rows ? 1.f : 0.f;
+    const bool lrow = lane < LDS::rows;
+    float nrm = 0.f;
 #pragma unroll
     for (int b4 = 0; b4 < NF / 4; ++b4) {
         float4 v = *reinterpret_cast<const float4 *>(&L.X[kr][4 * b4]);
-        v.x *= lv;
-        v.y *= lv;
-        v.z *= lv;
-        v.w *= lv;
-        xk[4 * b4 + 0] = v.x;
-        xk[4 * b4 + 1] = v.y;
-        xk[4 * b4 + 2] = v.z;
-        xk[4 * b4 + 3] = v.w;
+        if (!lrow) v = make_float4(0.f, 0.f, 0.f, 0.f);
         nrm = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, nrm))));
     }
     const float mx = __int_as_float(wave_max_key(__float_as_int(nrm)));  // nrm >= 0
     if (!(mx <= WB_AMP * lam)) return false;
-    // b_a = sum over kept k of x_ka y_k; then W = X with the unkept entries zeroed
+    // the lane's column: kept rows (bit k) and b_a = sum over kept k of x_ka y_k
+    uint32_t km = 0u;
     float b = 0.f;
-    bool keep[WB_D];
 #pragma unroll
     for (int k = 0; k < WB_D; ++k) {
         const float x = L.X[k][lane];
-        keep[k] = k < n && kept(c, key_of(x), tie_pos(L, 0, k));
-        if (keep[k]) b = fmaf(x, L.y[k], b);
+        const bool kp = k < n && kept(c, key_of(x), tie_pos(L, 0, k));
+        km |= kp ? (1u << k) : 0u;
+        b = fmaf(kp ? x : 0.f, L.y[k], b);
     }
-    if (lane >= nf) b = 0.f;
+    if (lane >= nf) {
+        b = 0.f;
+        km = 0u;
+    }
     wave_sync();
-    masked = true;
-#pragma unroll
-    for (int k = 0; k < WB_D; ++k)
-        if (!keep[k]) L.X[k][lane] = 0.f;
     L.urhs[lane] = b;
     wave_sync();
-    // G row `lane` and t_lane = x_lane . b
-    float G[WB_D];
+    // t_k = x_k . b
     float t = 0.f;
 #pragma unroll
     for (int b4 = 0; b4 < NF / 4; ++b4) {
+        float4 v = *reinterpret_cast<const float4 *>(&L.X[kr][4 * b4]);
+        if (!lrow) v = make_float4(0.f, 0.f, 0.f, 0.f);
         const float4 bv = *reinterpret_cast<const float4 *>(&L.urhs[4 * b4]);
-        t = fmaf(xk[4 * b4 + 0], bv.x, t);
-        t = fmaf(xk[4 * b4 + 1], bv.y, t);
-        t = fmaf(xk[4 * b4 + 2], bv.z, t);
-        t = fmaf(xk[4 * b4 + 3], bv.w, t);
+        t = fmaf(v.x, bv.x, t);
+        t = fmaf(v.y, bv.y, t);
+        t = fmaf(v.z, bv.z, t);
+        t = fmaf(v.w, bv.w, t);
     }
+    // G row `lane`
+    float G[WB_D];
 #pragma unroll
     for (int l = 0; l < WB_D; ++l) {
         float g = 0.f;
         if (l < n) {
-#pragma unroll
-            for (int b4 = 0; b4 < NF / 4; ++b4) {
-                const float4 wv = *reinterpret_cast<const float4 *>(&L.X[l][4 * b4]);
-                g = fmaf(xk[4 * b4 + 0], wv.x, g);
-                g = fmaf(xk[4 * b4 + 1], wv.y, g);
-                g = fmaf(xk[4 * b4 + 2], wv.z, g);
-                g = fmaf(xk[4 * b4 + 3], wv.w, g);
+            uint64_t cols = __ballot((km >> l) & 1u);  // the columns keeping row l
+            while (cols) {
+                const int a = __ffsll((unsigned long long)cols) - 1;
+                cols &= cols - 1;
+                g = fmaf(lrow ? L.X[kr][a] : 0.f, L.X[l][a], g);
             }
         }
         G[l] = g + (l == lane ? lamn : 0.f);
@@ -881,11 +878,11 @@ __device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, i
     if (!wb_lu(std::make_integer_sequence<int, WB_D>{}, G, t, lane, n, tol, zs)) return false;
     wave_sync();
     // u_a = (b_a - sum over kept k of x_ka z_k) / (lambda n)
-    float s = b;
+    float sacc = b;
 #pragma unroll
     for (int k = 0; k < WB_D; ++k)
-        if (k < n) s = fmaf(-L.X[k][lane], zs[k], s);
-    u = lane < nf ? s / lamn : 0.f;
+        if (k < n) sacc = fmaf(-(((km >> k) & 1u) ? L.X[k][lane] : 0.f), zs[k], sacc);
+    u = lane < nf ? sacc / lamn : 0.f;
     wave_sync();
     return true;
 }

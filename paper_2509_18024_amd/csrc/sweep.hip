@@ -48,11 +48,16 @@ __device__ __forceinline__ Cut select_for_class(LDS &L, RowCtx &r, int s, int la
 // the row index in `other`.
 // IMPL (implicit feedback): the system G + X*^T W X + lambda E with W =
 // diag(alpha y), right-hand side X*^T (1 + alpha y), G = a.G.
-template <int CLS, bool CHECK, bool STRIDED, bool FAST = false, bool IMPL = false>
+// WB: 1 (default) the two smallest classes try the Woodbury form first and
+// fall back to the n_f x n_f system in the same kernel; 2 Woodbury only,
+// rows it does not solve are listed for a second launch (which frees the
+// registers of the n_f x n_f solve); 0 never.
+template <int CLS, bool CHECK, bool STRIDED, bool FAST = false, bool IMPL = false, int WB = 1>
 __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
+    constexpr bool kWb = WB > 0 && !CHECK && !IMPL && (FAST || CLS == CLS_NET1 || CLS == CLS_NET2);
     // the two smallest classes solve in Woodbury form from one chunk of at
     // most WB_D rows: 32-row chunks, half the LDS per wavefront
-    using LDS = WaveLdsT<(!CHECK && !FAST && (CLS == CLS_NET1 || CLS == CLS_NET2)) ? WB_D : CK, FAST>;
+    using LDS = WaveLdsT<(kWb && !FAST) ? WB_D : CK, FAST>;
     __shared__ LDS lds[WPB];
     const int w = wave_index();
     const int lane0 = threadIdx.x & 63;
@@ -111,7 +116,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                 return;
             }
         }
-        if constexpr (!CHECK && !IMPL && (FAST || CLS == CLS_NET1 || CLS == CLS_NET2)) {
+        if constexpr (kWb) {
             // few entries: the n x n Woodbury form of the same system
             if (n <= WB_D && (FAST || s > 0) && a.lam > 0.f) {
                 stage(L, r, 0, lane);  // the whole row is chunk 0 (staged above)
@@ -122,6 +127,10 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                     return;
                 }
                 if (masked) r.staged = -1;  // L.X holds the masked rows: re-stage
+            }
+            if constexpr (WB == 2) {
+                if (lane == 0) a.fb_rows[atomicAdd(a.fb_count, 1u)] = (int32_t)i;
+                return;
             }
         }
         float A[NF];
@@ -206,11 +215,12 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
     } else {
         // persistent launch: each wavefront takes the next row of the class from
         // an atomic counter (rows are ordered by decreasing degree)
+        const int64_t cnt = a.count_dev ? (int64_t)*a.count_dev : a.count;
         for (;;) {
             unsigned int got = 0;
             if (lane0 == 0) got = atomicAdd(a.queue, 1u);
             const int64_t slot = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)got);
-            if (slot >= a.count) break;
+            if (slot >= cnt) break;
             const int lane = opaque_lane(lane0);
             const int64_t i = a.perm[slot];
             const int64_t beg = a.ptr[i];
@@ -231,7 +241,20 @@ __global__ __launch_bounds__(WPB * 64) void k_sweep_full(SweepArgs a) { sweep_ro
 // faster for them.
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_core(SweepArgs a) {
-    sweep_rows<CLS, false, CLS == CLS_NET1>(a);
+    sweep_rows<CLS, false, false>(a);
+}
+
+// The smallest class in Woodbury form only (rows it leaves go to k_sweep_rest).
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAVES, WB_WAVES))) void k_sweep_net1(
+    SweepArgs a) {
+    sweep_rows<CLS_NET1, false, true, false, false, 2>(a);
+}
+
+// Rows of a Woodbury class that the n x n form left (listed by the class's
+// launch): the n_f x n_f system, atomic queue over the list.
+template <int CLS>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_rest(SweepArgs a) {
+    sweep_rows<CLS, false, false, false, false, 0>(a);
 }
 
 // The second Woodbury class (rows of 20 to 29 entries at r = 1/10): more
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <int CLS>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WB_WAVES, WB_WAVES))) void k_sweep_wb(
     SweepArgs a) {
-    sweep_rows<CLS, false, false>(a);
+    sweep_rows<CLS, false, false, false, false, 2>(a);
 }
 
 // Light rows of the fast variant, every class in one launch (the schedule's
@@ -339,11 +362,25 @@ hipError_t launch_one(const SweepArgs &a, int max_blocks, hipStream_t s) {
         else {
             if constexpr (CLS == CLS_NET1) {
                 // rows are dealt out by wave index: the grid must be resident at once
-                const int64_t fit = resident_blocks(reinterpret_cast<const void *>(&k_sweep_core<CLS>));
+                const int64_t fit = resident_blocks(reinterpret_cast<const void *>(&k_sweep_net1));
                 if (fit <= 0) return hipErrorLaunchFailure;
                 if (blocks > fit) blocks = fit;
+                hipLaunchKernelGGL(k_sweep_net1, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+            } else {
+                hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
             }
-            hipLaunchKernelGGL(k_sweep_core<CLS>, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, a);
+        }
+        if constexpr (CLS == CLS_NET1 || CLS == CLS_NET2) {
+            // the rows the Woodbury form left, in a second persistent launch
+            // (grid for the worst case; each wave stops at the listed count)
+            if (!a.fb_rows || !a.fb_count || !a.fb_queue) return hipErrorInvalidValue;
+            SweepArgs b = a;
+            b.perm = a.fb_rows;
+            b.count_dev = a.fb_count;
+            b.queue = a.fb_queue;
+            int64_t fb = (a.count + WPB - 1) / WPB;
+            if (fb > 1024) fb = 1024;
+            hipLaunchKernelGGL(k_sweep_rest<CLS>, dim3((unsigned)fb), dim3(WPB * 64), 0, s, b);
         }
     }
     return hipGetLastError();
