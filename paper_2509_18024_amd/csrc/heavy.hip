@@ -510,6 +510,7 @@ __global__ __launch_bounds__(HS_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                 if (!S.done[tid]) S.T[tid] = S.prefix[tid];
                 S.ccnt[tid] = 0;
             }
+            __syncthreads();  // every thread has read the flag of the last pass
             if (tid == 0) S.flag = 0;
             __syncthreads();
             const bool tie = !S.done[lane] && S.ceq[lane] > S.rem[lane];

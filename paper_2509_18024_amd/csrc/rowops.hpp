@@ -346,7 +346,10 @@ __device__ __forceinline__ void gram_range_sparse(LDS &L, RowCtx &r, const Cut &
     for (int b = 0; b < NF; ++b) A[b] = 0.f;
     rhs = 0.f;
     if (c.none) return;
-    for (int k0 = kb; k0 < ke; k0 += LDS::rows) {
+    // chunks from the last one down: the selection leaves the last chunk of
+    // the row staged, so one gather of the row is saved
+    const int klast = kb + ((ke - kb - 1) / LDS::rows) * LDS::rows;
+    for (int k0 = klast; k0 >= kb; k0 -= LDS::rows) {
         stage(L, r, k0, lane);
         const int m = min(LDS::rows, ke - k0);
         uint64_t bits = 0;
