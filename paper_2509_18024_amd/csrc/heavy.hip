@@ -235,14 +235,30 @@ __device__ __forceinline__ bool heavy_pick_hint(HeavySelLds &S, int a) {
     if (S.done[a]) return true;
     const int rem = S.rem[a];
     int cum = 0, dsel = -1, hsel = 0;
-    for (int d = 255; d >= 0; --d) {
-        const int h = (int)((S.hist[d >> 1][a] >> ((d & 1) << 4)) & 0xFFFFu);
-        if (cum + h >= rem) {
-            dsel = d;
-            hsel = h;
-            break;
+    // eight words (sixteen bins) per batch, their LDS reads in flight together;
+    // word j holds bin 2j in its low and bin 2j + 1 in its high half
+    for (int w0 = 127; w0 >= 0 && dsel < 0; w0 -= 8) {
+        uint32_t wv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wv[q] = S.hist[w0 - q][a];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int hi = (int)(wv[q] >> 16), lo = (int)(wv[q] & 0xFFFFu);
+            if (dsel < 0) {
+                if (cum + hi >= rem) {
+                    dsel = 2 * (w0 - q) + 1;
+                    hsel = hi;
+                } else {
+                    cum += hi;
+                    if (cum + lo >= rem) {
+                        dsel = 2 * (w0 - q);
+                        hsel = lo;
+                    } else {
+                        cum += lo;
+                    }
+                }
+            }
         }
-        cum += h;
     }
     if (dsel < 0 || dsel == 255) return false;
     S.rem[a] = rem - cum;
