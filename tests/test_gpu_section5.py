@@ -1,13 +1,58 @@
 """The simulation workload of Section 5 at reduced size on the GPU: full ALS,
-CORE and UNIF trajectories against the FP64 oracle (same M0, same draws),
-and the paper's finding that CORE estimates better than UNIF at the same
-rate (Section 5.1), reported as ReMSE and P-ReMSE."""
+CORE and UNIF against the FP64 oracle, and the paper's finding that CORE
+estimates better than UNIF at the same rate (Section 5.1), reported as ReMSE
+and P-ReMSE.
+
+Two runs per method.  In the tracked run every GPU half-sweep starts from the
+oracle's factors of the step before (rounded to FP32) and must match the
+oracle's half-sweep to the FP32 bound (1e-4 relative Frobenius error).  The
+free run iterates on the GPU's own factors; its ReMSE is reported but not
+compared with the oracle's: the selection of Algorithm 1 ranks |x| within
+each column, so a half-sweep is a discontinuous function of the factors, and
+rounding-sized differences (relative 1e-6 per half-sweep, the size of FP32
+solves) that flip a near tie move the ReMSE of five CORE iterations by up to
+2e-3 on D2 and 7e-4 on D3 in the oracle itself.  The free runs carry the
+comparison of the methods (Section 5.1).
+
+UNIF's samples hold about n_f entries here (s = 20 for n_f = 20) and D2's
+factors are all positive and strongly correlated, so some UNIF systems are
+ill-conditioned; its tracked rows are held to the first-order FP32 bound of
+each row's system instead: relative error (max norm) at most
+kappa_inf * 2 (s + 3 n_f) 2^-24, with kappa_inf the condition number of the
+row's FP64 system (forming the sampled Gram costs s roundings per entry, the
+LU about 3 n_f)."""
 import numpy as np
 import pytest
 
 from paper_2509_18024_amd import synth
 
 gpu = pytest.mark.gpu
+
+
+def rel_fro(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def unif_rows_within_bound(ora, rp, ci, other, lam, seed, n_cols, G, O):
+    """Worst ratio of a row's max-norm relative error to its FP32 bound."""
+    ratio = 0.0
+    for i in range(len(rp) - 1):
+        cols = ci[rp[i]:rp[i + 1]]
+        n = len(cols)
+        s = ora.budget(n, 1, 10, 1)
+        if n == 0 or s == 0:
+            continue
+        keep = ora.unif_select(cols, i, n_cols, seed, s).astype(bool)
+        X = other[cols[keep]]
+        A = X.T @ X + lam * keep.sum() * np.eye(X.shape[1])
+        kappa = np.linalg.cond(A, np.inf)
+        den = np.abs(O[i]).max()
+        err = np.abs(np.asarray(G[i], np.float64) - O[i]).max() / (den if den > 0 else 1.0)
+        ratio = max(ratio, err / (kappa * 2 * (keep.sum() + 3 * X.shape[1]) * 2.0 ** -24))
+    return ratio
 
 
 @gpu
@@ -17,41 +62,61 @@ def test_section5_core_vs_unif_vs_full(ora, dist):
     from paper_2509_18024_amd.als import CoreALS
     prob, held = synth.section5(dist, 400, 400, 20, 0.5, 0.05, seed=620 + int(dist[1]))
     cp, ri, vt = ora.transpose(prob.n_u, prob.n_m, prob.row_ptr, prob.col_idx, prob.val)
-    hcp = ora.transpose(prob.n_u, prob.n_m, *held)
     iters = 5
     res = {}
     for method, budget in (("full", (1, 1)), ("core", (1, 10)), ("unif", (1, 10))):
         als = CoreALS.from_problem(prob, "cuda", budget=budget, unif=(method == "unif"))
-        M = torch.from_numpy(prob.M0).cuda()
-        Mo = prob.M0.astype(np.float64)
-        U = torch.empty(prob.n_u, prob.n_f, device="cuda")
-        for t in range(iters):
+
+        def users(M, Mo, t):
             if method == "unif":
                 als.set_sample_seed(2 * t)
                 Uo, _ = ora.unif_half_sweep(prob.row_ptr, prob.col_idx, prob.val, Mo, prob.lam, *budget, 1, 2 * t)
             else:
                 Uo, _ = ora.half_sweep(prob.row_ptr, prob.col_idx, prob.val, Mo, prob.lam, *budget, 1)
-            als.half_sweep_users(M, U)
+            return als.half_sweep_users(M), Uo
+
+        def items(U, Uo, t):
             if method == "unif":
                 als.set_sample_seed(2 * t + 1)
                 Mo, _ = ora.unif_half_sweep(cp, ri, vt, Uo, prob.lam, *budget, 1, 2 * t + 1)
             else:
                 Mo, _ = ora.half_sweep(cp, ri, vt, Uo, prob.lam, *budget, 1)
-            als.half_sweep_items(U, M)
+            return als.half_sweep_items(U), Mo
+
+        # tracked run: each GPU half-sweep from the oracle's previous factors
+        Mo = prob.M0.astype(np.float64)
+        worst = 0.0  # full, CORE: relative Frobenius error; UNIF: worst row over its bound
+        for t in range(iters):
+            M32 = Mo.astype(np.float32)
+            U, Uo = users(torch.from_numpy(M32).cuda(), Mo, t)
+            U32 = Uo.astype(np.float32)
+            M, Mo_next = items(torch.from_numpy(U32).cuda(), Uo, t)
+            if method == "unif":
+                worst = max(worst, unif_rows_within_bound(ora, prob.row_ptr, prob.col_idx, M32.astype(np.float64),
+                                                          prob.lam, 2 * t, prob.n_m, U.cpu().numpy(), Uo),
+                            unif_rows_within_bound(ora, cp, ri, U32.astype(np.float64), prob.lam, 2 * t + 1,
+                                                   prob.n_u, M.cpu().numpy(), Mo_next))
+            else:
+                worst = max(worst, rel_fro(U.cpu().numpy(), Uo), rel_fro(M.cpu().numpy(), Mo_next))
+            Mo = Mo_next
+        remse_o = ora.objective(prob.row_ptr, prob.col_idx, prob.val, Uo, Mo, prob.lam)[3]
+        # free run on the GPU's own factors (the draws of UNIF as in the oracle's)
+        M = torch.from_numpy(prob.M0).cuda()
+        for t in range(iters):
+            if method == "unif":
+                als.set_sample_seed(2 * t)
+            U = als.half_sweep_users(M)
+            if method == "unif":
+                als.set_sample_seed(2 * t + 1)
+            M = als.half_sweep_items(U)
         torch.cuda.synchronize()
         Ug, Mg = U.cpu().numpy().astype(np.float64), M.cpu().numpy().astype(np.float64)
         remse = ora.objective(prob.row_ptr, prob.col_idx, prob.val, Ug, Mg, prob.lam)[3]
-        remse_o = ora.objective(prob.row_ptr, prob.col_idx, prob.val, Uo, Mo, prob.lam)[3]
         p_remse = ora.objective(*held, Ug, Mg, prob.lam)[3]
         res[method] = (remse, p_remse)
-        print(f"[section5 {dist}] {method}: ReMSE {remse:.5f} (oracle {remse_o:.5f}), P-ReMSE {p_remse:.5f}",
-              flush=True)
-        # the GPU and the oracle run the same trajectory (same M0, same draws).
-        # UNIF's samples hold about n_f entries here (s = 20 for n_f = 20), so
-        # its systems are ill-conditioned (D2's factors are all positive and
-        # strongly correlated) and the FP32 solves drift further from FP64.
-        tol = 5e-2 if method == "unif" else 1e-3
-        assert abs(remse - remse_o) <= tol * max(1.0, remse_o)
+        print(f"[section5 {dist}] {method}: tracked half-sweeps worst {worst:.1e}; free run ReMSE {remse:.5f} "
+              f"(oracle {remse_o:.5f}), P-ReMSE {p_remse:.5f}", flush=True)
+        assert worst <= (1.0 if method == "unif" else 1e-4)
         als.close()
     # Section 5.1: CORE beats UNIF at the same rate; full ALS is the floor
     assert res["core"][0] < res["unif"][0] and res["core"][1] < res["unif"][1]
