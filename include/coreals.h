@@ -168,6 +168,10 @@ typedef struct {
                                     window around the same row's threshold of the
                                     previous half-sweep of this side (the cuts are
                                     exact either way)                             */
+    int64_t n_pivoted;           /* light core rows whose elimination without row
+                                    exchanges was rejected (a small pivot, or an
+                                    entry grown beyond 4 max|A|) and that were
+                                    solved again with partial pivoting            */
 } als_sweep_stats;
 
 typedef struct {

@@ -48,7 +48,7 @@ class als_sweep_stats(ctypes.Structure):
     _fields_ = [("n_empty", ctypes.c_int64), ("n_singular_fallback", ctypes.c_int64),
                 ("n_fp64_residual", ctypes.c_int64), ("n_rows", ctypes.c_int64),
                 ("n_fp32_gram", ctypes.c_int64), ("max_rel_residual", ctypes.c_double),
-                ("n_select_hinted", ctypes.c_int64)]
+                ("n_select_hinted", ctypes.c_int64), ("n_pivoted", ctypes.c_int64)]
 
 
 class als_objective(ctypes.Structure):

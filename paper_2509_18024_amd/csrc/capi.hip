@@ -525,6 +525,7 @@ als_status fill_stats(als_ctx *c, int side, const unsigned long long *stats, als
     std::memcpy(&mr, &h[ST_MAXRES], sizeof(mr));
     st->max_rel_residual = mr;
     st->n_select_hinted = (int64_t)h[ST_HINTED];
+    st->n_pivoted = (int64_t)h[ST_PIVOTED];
     return ALS_OK;
 }
 

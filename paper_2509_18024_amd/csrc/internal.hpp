@@ -133,7 +133,8 @@ enum StatSlot : int {
     ST_FP32GRAM = 5,
     ST_MAXRES = 6,  // bits of the largest relative refinement residual (non-negative double)
     ST_HINTED = 7,  // heavy rows whose selection started from the previous cuts
-    NSTATS = 8
+    ST_PIVOTED = 8, // light core rows whose unpivoted elimination was rejected
+    NSTATS = 10
 };
 
 struct SweepArgs {

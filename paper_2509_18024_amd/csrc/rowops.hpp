@@ -696,6 +696,53 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
     return ok;
 }
 
+// Gaussian elimination without row exchanges (row J is the pivot of step J),
+// accepted only when no pivot is small, no entry of the eliminated matrix
+// exceeds UNPIV_GROWTH times the largest entry of A and no multiplier
+// exceeds UNPIV_MULT in magnitude: with |L| and |U| so bounded, the computed
+// factors have the backward error bound of the pivoted LU up to those
+// factors.  Returns false otherwise; A is then spent and the caller builds
+// the system again for the pivoted LU.
+constexpr float UNPIV_GROWTH = 4.f;
+constexpr float UNPIV_MULT = 4.f;
+template <class LDS>
+__device__ __forceinline__ bool solve_unpivoted(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
+                                                LDS &L) {
+    float amax = 0.f;
+#pragma unroll
+    for (int b = 0; b < NF; ++b) amax = fmaxf(amax, fabsf(A[b]));
+    amax = __int_as_float(wave_max_key(__float_as_int(amax)));
+    int my_step = NF;
+    bool ok = true;
+    float r[1] = {rhs};
+    elim_all_u<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok);
+    float g = 0.f;
+#pragma unroll
+    for (int b = 0; b < NF; ++b) g = fmaxf(g, fabsf(A[b]));
+    g = __int_as_float(wave_max_key(__float_as_int(g)));
+    if (!ok || !(g <= UNPIV_GROWTH * amax)) return false;
+    // the multipliers, from what the elimination left: column J of a row
+    // below J still holds that row's entry when it was eliminated, l u_JJ,
+    // and row J holds u_JJ
+    uint64_t big = 0;
+#pragma unroll
+    for (int j0 = 0; j0 < NF; j0 += 8) {
+        float ud[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) ud[t] = readlane_f(A[j0 + t], j0 + t);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) big |= __ballot(lane > j0 + t && fabsf(A[j0 + t]) > UNPIV_MULT * fabsf(ud[t]));
+    }
+    if (big) return false;
+    my_step = lane;
+    wave_sync();
+    back_all_u<false, 1>(std::make_integer_sequence<int, NF>{}, A, r, lane, my_step, L.urhs);
+    wave_sync();
+    u = L.urhs[lane];
+    wave_sync();
+    return true;
+}
+
 // Pivoted LU that keeps its factors in A (multipliers below, U above the
 // pivots) and the lane's pivot step in my_step; returns false on a pivot of
 // the first nf steps <= tol.

@@ -136,10 +136,12 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
         float A[NF];
         float rhs;
         float u = 0.f;
-        // attempt 0: the core system; attempt 1 (core rows whose system is
-        // singular): the full-data update of eq. (U)
+        // attempt 0: the core system by elimination without row exchanges;
+        // attempt 1 (growth or a small pivot): the same system, pivoted LU;
+        // attempt 2 (core rows whose system is singular): the full-data
+        // update of eq. (U)
 #pragma unroll 1
-        for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int attempt = 0; attempt < 3; ++attempt) {
             if constexpr (IMPL) {
                 gram_range_sparse<LDS, true>(L, r, c, 0, n, lane, A, rhs, a.alpha);
                 finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
@@ -148,12 +150,21 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs &a) {
                 else gram(L, r, c, lane, A, rhs);
                 finish_system(A, rhs, lamn, lane, a.nf);
             }
-            const bool ok = solve<kCore>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            bool ok;
+            if constexpr (kCore) {
+                if (attempt == 0) ok = solve_unpivoted(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+                else ok = solve<true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            } else {
+                ok = solve<false>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            }
             if (ok) break;
             u = 0.f;
-            if (!kCore || attempt == 1) break;
-            if (lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
-            c = Cut{0, 0, false, true};
+            if (!kCore || attempt == 2) break;
+            if (attempt == 0 && lane == 0) atomicAdd(&a.stats[ST_PIVOTED], 1ull);
+            if (attempt == 1) {
+                if (lane == 0) atomicAdd(&a.stats[ST_FALLBACK], 1ull);
+                c = Cut{0, 0, false, true};
+            }
         }
         if (lane < a.nf) a.out[i * a.nf + lane] = u;
     };

@@ -409,6 +409,9 @@ def test_empty_rows_and_singular_fallback(ora):
          f"rel err {rel_fro(Ug, Uo):.2e}")
     assert st.n_empty == 5 and sto[0] == 5
     assert st.n_singular_fallback == sto[1] == p.n_u - 8
+    # every singular light core system was first rejected by the elimination
+    # without row exchanges (user 10, the heavy row, is solved pivoted at once)
+    assert st.n_pivoted >= st.n_singular_fallback - 1
     assert np.all(Ug[:10] == 0) and np.all(Uo[:10] == 0)
     # the fallback rows (eq. (U), least squares at lambda = 0) element by element
     assert rel_fro(Ug[10:], Uo[10:]) <= 1e-4
