@@ -788,19 +788,28 @@ __device__ __forceinline__ int wb_pivot_key(const float (&G)[WB_D], int lane, in
     return wave_max_key(cand);
 }
 
-// pk: the pivot key of column J, computed by the previous step (lookahead as
-// in elim_step_u); on return, that of column J + 1.
-template <int J>
+// PIV: pivoted; pk is the pivot key of column J, computed by the previous
+// step (lookahead as in elim_step_u), and on return that of column J + 1.
+// Otherwise row J is the pivot of step J.
+template <int J, bool PIV>
 __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lane, int n, float tol, int &my_step,
                                              bool &ok, int &pk) {
     if (J >= n) return;  // uniform: the system has n rows
-    const bool active = my_step == WB_D + 1;
-    const int p = 63 - (pk & 63);
+    bool active;
+    int p;
+    if constexpr (PIV) {
+        active = my_step == WB_D + 1;
+        p = 63 - (pk & 63);
+    } else {
+        active = lane > J;
+        p = J;
+    }
     const float piv = readlane_f(G[J], p);
     ok = ok && fabsf(piv) > tol;
     const bool elim = active && lane != p;
     const float l = elim ? G[J] * __builtin_amdgcn_rcpf(piv) : 0.f;
-    if (lane == p) my_step = J;
+    if constexpr (PIV)
+        if (lane == p) my_step = J;
     // columns n.. of every row stay as they are: the pivot row is zero there
 #pragma unroll
     for (int c0 = J + 1; c0 < WB_D; c0 += 8) {  // batched as in elim_step_u
@@ -812,34 +821,63 @@ __device__ __forceinline__ void wb_elim_step(float (&G)[WB_D], float &t, int lan
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (c0 + k < WB_D) G[c0 + k] = fmaf(-l, pr[k], G[c0 + k]);
-        if constexpr (J + 1 < WB_D)
+        if constexpr (PIV && J + 1 < WB_D)
             if (c0 == J + 1) pk = wb_pivot_key<J + 1>(G, lane, my_step);  // column J + 1 is final (J + 1 < n)
     }
     t = fmaf(-l, readlane_f(t, p), t);
 }
 
-template <int J>
+template <int J, bool PIV>
 __device__ __forceinline__ void wb_back_step(const float (&G)[WB_D], float &t, int lane, int n, int my_step,
                                              float *zs) {
     if (J >= n) return;
-    asm volatile("" : "+v"(my_step));
-    const uint64_t bal = __ballot(my_step == J);
-    int p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
-    p = __builtin_amdgcn_readfirstlane(p);
+    int p;
+    if constexpr (PIV) {
+        asm volatile("" : "+v"(my_step));
+        const uint64_t bal = __ballot(my_step == J);
+        p = bal ? (__ffsll((unsigned long long)bal) - 1) : 0;
+        p = __builtin_amdgcn_readfirstlane(p);
+    } else {
+        p = J;
+    }
     const float x = readlane_f(t, p) * __builtin_amdgcn_rcpf(readlane_f(G[J], p));
     if (lane == 0) zs[J] = x;
     if (my_step < J) t = fmaf(-G[J], x, t);
 }
 
-template <int... J>
+// PIV false: elimination without row exchanges, kept only under the bounds of
+// solve_unpivoted (no small pivot, entries of the eliminated rows within
+// UNPIV_GROWTH gm, multipliers within UNPIV_MULT); gm = max |G| before.
+// Returns false on a rejection or a small pivot; G and t are then spent.
+template <bool PIV, int... J>
 __device__ __forceinline__ bool wb_lu(std::integer_sequence<int, J...>, float (&G)[WB_D], float &t, int lane, int n,
-                                      float tol, float *zs) {
+                                      float tol, float gm, float *zs) {
     int my_step = WB_D + 1;
     bool ok = true;
-    int pk = wb_pivot_key<0>(G, lane, my_step);
-    (wb_elim_step<J>(G, t, lane, n, tol, my_step, ok, pk), ...);
+    int pk = PIV ? wb_pivot_key<0>(G, lane, my_step) : 0;
+    (wb_elim_step<J, PIV>(G, t, lane, n, tol, my_step, ok, pk), ...);
     if (!ok) return false;
-    (wb_back_step<WB_D - 1 - J>(G, t, lane, n, my_step, zs), ...);
+    if constexpr (!PIV) {
+        float g = 0.f;
+#pragma unroll
+        for (int l = 0; l < WB_D; ++l) g = fmaxf(g, fabsf(G[l]));
+        g = __int_as_float(wave_max_key(__float_as_int(lane < n ? g : 0.f)));
+        if (!(g <= UNPIV_GROWTH * gm)) return false;
+        // multipliers: column J of a row below J holds l u_JJ, row J holds u_JJ
+        uint64_t big = 0;
+#pragma unroll
+        for (int j0 = 0; j0 < WB_D; j0 += 8) {
+            float ud[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ud[q] = readlane_f(G[j0 + q], j0 + q);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                big |= __ballot(j0 + q < n && lane > j0 + q && fabsf(G[j0 + q]) > UNPIV_MULT * fabsf(ud[q]));
+        }
+        if (big) return false;
+        my_step = lane;
+    }
+    (wb_back_step<WB_D - 1 - J, PIV>(G, t, lane, n, my_step, zs), ...);
     return true;
 }
 
@@ -898,34 +936,41 @@ __device__ __forceinline__ bool woodbury_solve(LDS &L, const Cut &c, int lane, i
         t = fmaf(v.z, bv.z, t);
         t = fmaf(v.w, bv.w, t);
     }
-    // G row `lane`
+    // G row `lane` (rows n.. of the padded system are identity rows)
     float G[WB_D];
+    auto build_g = [&]() {
 #pragma unroll
-    for (int l = 0; l < WB_D; ++l) {
-        float g = 0.f;
-        if (l < n) {
-            uint64_t cols = __ballot((km >> l) & 1u);  // the columns keeping row l
-            while (cols) {
-                const int a = __ffsll((unsigned long long)cols) - 1;
-                cols &= cols - 1;
-                g = fmaf(lrow ? L.X[kr][a] : 0.f, L.X[l][a], g);
+        for (int l = 0; l < WB_D; ++l) {
+            float g = 0.f;
+            if (l < n) {
+                uint64_t cols = __ballot((km >> l) & 1u);  // the columns keeping row l
+                while (cols) {
+                    const int a = __ffsll((unsigned long long)cols) - 1;
+                    cols &= cols - 1;
+                    g = fmaf(lrow ? L.X[kr][a] : 0.f, L.X[l][a], g);
+                }
             }
+            G[l] = g + (l == lane ? lamn : 0.f);
         }
-        G[l] = g + (l == lane ? lamn : 0.f);
-    }
-    // rows n.. of the padded system are identity rows
-    if (lane >= n) {
+        if (lane >= n) {
 #pragma unroll
-        for (int l = 0; l < WB_D; ++l) G[l] = (l == lane) ? 1.f : 0.f;
-        t = 0.f;
-    }
+            for (int l = 0; l < WB_D; ++l) G[l] = (l == lane) ? 1.f : 0.f;
+        }
+    };
+    build_g();
+    if (lane >= n) t = 0.f;
     float gm = 0.f;
 #pragma unroll
     for (int l = 0; l < WB_D; ++l) gm = fmaxf(gm, fabsf(G[l]));
     gm = __int_as_float(wave_max_key(__float_as_int(gm)));
     const float tol = (float)n * 1.1920928955078125e-7f * gm;
     float *zs = &L.urhs[NF];  // z_k, written by lane 0 of the back substitution
-    if (!wb_lu(std::make_integer_sequence<int, WB_D>{}, G, t, lane, n, tol, zs)) return false;
+    const float t0 = t;
+    if (!wb_lu<false>(std::make_integer_sequence<int, WB_D>{}, G, t, lane, n, tol, gm, zs)) {
+        build_g();  // the elimination without row exchanges was rejected: pivoted LU
+        t = t0;
+        if (!wb_lu<true>(std::make_integer_sequence<int, WB_D>{}, G, t, lane, n, tol, gm, zs)) return false;
+    }
     wave_sync();
     // u_a = (b_a - sum over kept k of x_ka z_k) / (lambda n)
     float sacc = b;

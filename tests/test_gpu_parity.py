@@ -420,6 +420,49 @@ def test_empty_rows_and_singular_fallback(ora):
 
 
 @gpu
+def test_rows_rejected_by_the_elimination_without_row_exchanges(ora):
+    """Latent column 5 of the item factors a thousand times smaller than the
+    others and lambda = 1e-4: in about half of the 64 x 64 core systems the
+    elimination without row exchanges meets multipliers far above 4 at that
+    column (the entries below the diagonal are about 1e3 times the diagonal
+    entry), so those rows are solved again with partial pivoting.  All rows,
+    either way, against the FP64 oracle; with kappa_inf up to about 1e5 here,
+    each row is held to the first-order FP32 bound of its own system,
+    kappa_inf 2 (s + 3 n_f) 2^-24 in the max norm (s roundings per entry of
+    the Gram, about 3 n_f in the LU)."""
+    from oracle.foldin import core_system
+    import dataclasses
+    import torch
+    p = synth.random_problem(77, 200, 400, 32, 0.15, lam=1e-4, budget=(1, 10))
+    M0 = p.M0.copy()
+    M0[:, 5] *= np.float32(1e-3)
+    p = dataclasses.replace(p, M0=M0)
+    deg = np.diff(p.row_ptr)
+    lu_rows = int(np.sum((deg > 32) & (deg <= 1024)))  # rows of more than 32 entries: the 64 x 64 system
+    als = make_als(p)
+    U, st = als.half_sweep_users(torch.from_numpy(M0).cuda(), stats=True)
+    torch.cuda.synchronize()
+    Uo, sto = ora.half_sweep(p.row_ptr, p.col_idx, p.val, M0.astype(np.float64), p.lam, 1, 10, 1)
+    Ug = U.cpu().numpy()
+    note(f"[pivoted retry] {st.n_pivoted} of {lu_rows} rows pivoted, fallback {st.n_singular_fallback}/{sto[1]}, "
+         f"rel err {rel_fro(Ug, Uo):.2e}")
+    assert lu_rows > 150 and lu_rows // 4 <= st.n_pivoted < lu_rows
+    assert st.n_singular_fallback == sto[1] == 0
+    worst = 0.0
+    for i in range(p.n_u):
+        c = p.col_idx[p.row_ptr[i]:p.row_ptr[i + 1]]
+        n = len(c)
+        s = ora.budget(n, 1, 10, 1)
+        A, _ = core_system(M0[c].astype(np.float64), p.val[p.row_ptr[i]:p.row_ptr[i + 1]], p.lam, s)
+        bound = np.linalg.cond(A, np.inf) * 2 * (s + 3 * p.n_f) * 2.0 ** -24
+        err = np.abs(Ug[i] - Uo[i]).max() / np.abs(Uo[i]).max()
+        worst = max(worst, err / bound)
+    note(f"  worst row error over its FP32 bound {worst:.2e}")
+    assert worst <= 1.0
+    als.close()
+
+
+@gpu
 def test_validation_errors():
     import torch
     from paper_2509_18024_amd import capi
