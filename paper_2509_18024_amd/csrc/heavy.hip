@@ -27,7 +27,8 @@
 //                    scratch (column-major: element (a, b) at b * 64 + a).
 //   k_heavy_solve    one wavefront per row sums its partial systems in chunk
 //                    order (deterministic), adds lambda n_i, and solves it
-//                    (pivoted LU).
+//                    (blocked elimination without row exchanges under growth
+//                    and multiplier bounds, else pivoted LU).
 //
 // BF16 precision modes run k_heavy_gram_x6 with one product per tile (the
 // operands' bf16 roundings, FP32 accumulation) and add one step of iterative
@@ -612,17 +613,21 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
         // (fast variant: every row's sketch is a core system)
         float *fac = a.partials + (a.pair_off[slot] - pair_base) * (int64_t)(NF + 1) * 64;
         float A[NF];
-        float rhs = 0.f;
+        float rhs;
+        auto build = [&]() {
+            rhs = 0.f;
 #pragma unroll
-        for (int b = 0; b < NF; ++b) A[b] = 0.f;
-        for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p) {
-            const float *src = a.partials + (p - pair_base) * (int64_t)(NF + 1) * 64;
+            for (int b = 0; b < NF; ++b) A[b] = 0.f;
+            for (int64_t p = a.pair_off[slot]; p < a.pair_off[slot + 1]; ++p) {
+                const float *src = a.partials + (p - pair_base) * (int64_t)(NF + 1) * 64;
 #pragma unroll
-            for (int b = 0; b < NF; ++b) A[b] += src[b * 64 + lane];
-            rhs += src[NF * 64 + lane];
-        }
-        if (a.implicit) finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
-        else finish_system(A, rhs, lamn, lane, a.nf);
+                for (int b = 0; b < NF; ++b) A[b] += src[b * 64 + lane];
+                rhs += src[NF * 64 + lane];
+            }
+            if (a.implicit) finish_system_implicit(A, rhs, a.G, a.lam, lane, a.nf);
+            else finish_system(A, rhs, lamn, lane, a.nf);
+        };
+        build();
         float u = 0.f;
         const bool core = !a.unif && (a.gpos || s < n);
         bool ok;
@@ -660,7 +665,14 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
                 if (regram) atomicAdd(&a.stats[ST_FP32GRAM], 1ull);
             }
         } else {
-            ok = solve<true, WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            // elimination without row exchanges first (bounds as for light
+            // rows); when rejected, the system is summed again for the
+            // pivoted LU, which decides singularity
+            ok = solve_unpivoted<WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            if (!ok) {
+                build();
+                ok = solve<true, WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
+            }
         }
         if (!ok) {
             u = 0.f;

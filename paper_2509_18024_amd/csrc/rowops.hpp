@@ -705,7 +705,8 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
 // the system again for the pivoted LU.
 constexpr float UNPIV_GROWTH = 4.f;
 constexpr float UNPIV_MULT = 4.f;
-template <class LDS>
+// BLOCKED: panels as in solve_n (the heavy-row solve).
+template <class LDS, bool BLOCKED = false>
 __device__ __forceinline__ bool solve_unpivoted(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
                                                 LDS &L) {
     float amax = 0.f;
@@ -715,7 +716,10 @@ __device__ __forceinline__ bool solve_unpivoted(float (&A)[NF], float rhs, int l
     int my_step = NF;
     bool ok = true;
     float r[1] = {rhs};
-    elim_all_u<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok);
+    if constexpr (BLOCKED)
+        blk_all<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok, L.pbuf);
+    else
+        elim_all_u<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok);
     float g = 0.f;
 #pragma unroll
     for (int b = 0; b < NF; ++b) g = fmaxf(g, fabsf(A[b]));
