@@ -168,12 +168,13 @@ typedef struct {
                                     window around the same row's threshold of the
                                     previous half-sweep of this side (the cuts are
                                     exact either way)                             */
-    int64_t n_pivoted;           /* light core rows whose elimination without row
-                                    exchanges was rejected (a small pivot, an entry
-                                    grown beyond 4 max|A| or a multiplier above 4)
-                                    and that were solved again with partial
-                                    pivoting (the n x n systems of rows of at most
-                                    32 entries retry the same way, uncounted)     */
+    int64_t n_pivoted;           /* rows whose elimination without row exchanges
+                                    was rejected (a small pivot, an entry grown
+                                    beyond 4 max|A| or a multiplier above 4) and
+                                    that were solved again with partial pivoting:
+                                    light core rows and heavy rows (the n x n
+                                    systems of rows of at most 32 entries retry
+                                    the same way, uncounted)                      */
 } als_sweep_stats;
 
 typedef struct {

@@ -670,6 +670,7 @@ __global__ __launch_bounds__(WPB * 64) void k_heavy_solve(HeavyArgs a, int64_t s
             // pivoted LU, which decides singularity
             ok = solve_unpivoted<WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
             if (!ok) {
+                if (lane == 0) atomicAdd(&a.stats[ST_PIVOTED], 1ull);
                 build();
                 ok = solve<true, WaveLds, true>(A, rhs, lane, a.nf, system_tol(A, a.nf), u, L);
             }

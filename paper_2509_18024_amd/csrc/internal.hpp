@@ -133,7 +133,7 @@ enum StatSlot : int {
     ST_FP32GRAM = 5,
     ST_MAXRES = 6,  // bits of the largest relative refinement residual (non-negative double)
     ST_HINTED = 7,  // heavy rows whose selection started from the previous cuts
-    ST_PIVOTED = 8, // light core rows whose unpivoted elimination was rejected
+    ST_PIVOTED = 8, // light core and heavy rows whose unpivoted elimination was rejected
     NSTATS = 10
 };
 

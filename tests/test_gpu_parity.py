@@ -409,9 +409,9 @@ def test_empty_rows_and_singular_fallback(ora):
          f"rel err {rel_fro(Ug, Uo):.2e}")
     assert st.n_empty == 5 and sto[0] == 5
     assert st.n_singular_fallback == sto[1] == p.n_u - 8
-    # every singular light core system was first rejected by the elimination
-    # without row exchanges (user 10, the heavy row, is solved pivoted at once)
-    assert st.n_pivoted >= st.n_singular_fallback - 1
+    # every singular core system, the heavy row's too, was first rejected by
+    # the elimination without row exchanges and summed or built again
+    assert st.n_pivoted >= st.n_singular_fallback
     assert np.all(Ug[:10] == 0) and np.all(Uo[:10] == 0)
     # the fallback rows (eq. (U), least squares at lambda = 0) element by element
     assert rel_fro(Ug[10:], Uo[10:]) <= 1e-4
@@ -438,7 +438,7 @@ def test_rows_rejected_by_the_elimination_without_row_exchanges(ora):
     M0[:, 5] *= np.float32(1e-3)
     p = dataclasses.replace(p, M0=M0)
     deg = np.diff(p.row_ptr)
-    lu_rows = int(np.sum((deg > 32) & (deg <= 1024)))  # rows of more than 32 entries: the 64 x 64 system
+    lu_rows = int(np.sum(deg > 32))  # rows of more than 32 entries: the 64 x 64 system
     als = make_als(p)
     U, st = als.half_sweep_users(torch.from_numpy(M0).cuda(), stats=True)
     torch.cuda.synchronize()
