@@ -59,6 +59,7 @@ def main() -> None:
     ap.add_argument("--skip", type=int, default=0, help="leading dispatches of each kernel to leave out")
     ap.add_argument("--kernels", nargs="+", default=["k_heavy_select", "k_heavy_gram_x6"])
     ap.add_argument("--workload", default="c3_batched core r=1/10 fp32")
+    ap.add_argument("--out", default=OUT, help="digest file (default: next to this script)")
     args = ap.parse_args()
 
     sys.path.insert(0, ROOT)
@@ -92,7 +93,7 @@ def main() -> None:
         lines.append(f"| `{k}` WRITE_SIZE per dispatch (KiB) | {' / '.join(f'{v:.0f}' for v in wv)} |")
         lines.append(f"| `{k}` scaled HBM bytes per launch (mean over {len(fv)} dispatches) | "
                      f"{(fb + wb) / 1e9:.3f} GB (fetch {fb / 1e9:.3f} + write {wb / 1e9:.3f}) |")
-    with open(OUT, "w") as f:
+    with open(args.out, "w") as f:
         json.dump(digest, f, indent=1)
     print("\n".join(lines))
 

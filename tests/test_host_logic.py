@@ -73,3 +73,59 @@ def test_binding_constants_match_the_header():
     for name in ("ALS_VALIDATE", "ALS_USERS_ONLY", "ALS_GENERIC_GATHERS", "ALS_OK", "ALS_E_ARG",
                  "ALS_E_STATE", "ALS_PREC_FP32", "ALS_PREC_BF16_IR", "ALS_PREC_AUTO"):
         assert hasattr(capi, name), name
+
+
+def _counter_csv(path, rows):
+    """A rocprofv3 counter_collection.csv with the columns the digest reads."""
+    import csv
+    path.mkdir(parents=True, exist_ok=True)
+    with open(path / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, k, c, v in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_traffic_digest_scales_by_the_copy_kernel(tmp_path):
+    """The copy kernel moves 1 GiB each way; its readings fix one factor per
+    counter, and a kernel's bytes per launch are the means of its dispatches
+    after the skipped ones, each counter times its factor."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    kib = float(1 << 20)  # 1 GiB in KiB
+    ew = "void at::native::elementwise_kernel<...>"
+    _counter_csv(tmp_path / "cf", [(1, ew, "FETCH_SIZE", kib / 2), (2, ew, "FETCH_SIZE", kib / 2)])  # factor 2
+    _counter_csv(tmp_path / "cw", [(1, ew, "WRITE_SIZE", kib)])                                      # factor 1
+    k = "void coreals::k_heavy_select<true, true>(coreals::HeavyArgs, long)"
+    _counter_csv(tmp_path / "f", [(1, k, "FETCH_SIZE", 999.0), (3, k, "FETCH_SIZE", 100.0),
+                                  (5, k, "FETCH_SIZE", 300.0)])
+    _counter_csv(tmp_path / "w", [(1, k, "WRITE_SIZE", 999.0), (3, k, "WRITE_SIZE", 10.0),
+                                  (5, k, "WRITE_SIZE", 30.0)])
+    out = tmp_path / "digest.json"
+    subprocess.run([sys.executable, os.path.join(root, "paper_2509_18024_amd", "tuning", "traffic_digest.py"),
+                    "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"),
+                    "--copy-fetch", str(tmp_path / "cf"), "--copy-write", str(tmp_path / "cw"),
+                    "--skip", "1", "--kernels", "k_heavy_select", "--out", str(out)],
+                   check=True, stdout=subprocess.PIPE)
+    d = json.load(open(out))
+    assert d["fetch_factor"] == 2.0 and d["write_factor"] == 1.0
+    e = d["kernels"]["k_heavy_select"]
+    assert e["dispatches"] == 2
+    assert e["fetch_bytes_per_launch"] == 200.0 * 1024 * 2.0   # mean of 100 and 300 KiB, doubled
+    assert e["write_bytes_per_launch"] == 20.0 * 1024
+    assert e["hbm_bytes_per_launch"] == e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+def test_traffic_figure_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
+    import bench
+    path = tmp_path / "t.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.measured_traffic("k_heavy_select") is None  # no digest
+    entry = {"kernels": {"k_heavy_select": {"hbm_bytes_per_launch": 5.0}}}
+    json.dump(dict(entry, source_sha256=bench.kernel_source_digest()), open(path, "w"))
+    assert bench.measured_traffic("k_heavy_select") == 5.0
+    assert bench.measured_traffic("k_heavy_gram_x6") is None
+    json.dump(dict(entry, source_sha256="0" * 64), open(path, "w"))
+    assert bench.measured_traffic("k_heavy_select") is None  # taken on other sources
