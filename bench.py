@@ -290,7 +290,7 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
             u0 += b
         stream.synchronize()
 
-        def run(with_net):
+        def run(with_net, tol_run=tol):
             outs, rhos, paths, kept = [], [], [], 0
             stream.synchronize()
             t = time.perf_counter()
@@ -298,7 +298,7 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
                 q = CoreALS(b, prob.n_m, prob.n_f, brp, bci, bv, prob.lam, budget, prob.min_keep,
                             1, validate=False, stream=stream, users_only=True)
                 if with_net:
-                    U, path, rho, st = net.answer(q, M, tol=tol, stats=False)
+                    U, path, rho, st = net.answer(q, M, tol=tol_run, stats=False)
                     rhos.append(rho)
                     paths.append(path)
                 else:
@@ -311,6 +311,9 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
         run(True)  # warm-up of every code path
         t_net, U_net, rhos, paths = run(True)
         t_exact, U_ex, _, _ = run(False)
+        # the same arrivals at looser tolerances: what the network path gains
+        # where it keeps most answers
+        t_loose = {t: run(True, t)[0] for t in (1e-1, 3e-1)}
         rho = torch.cat(rhos).cpu().numpy()
         path = torch.cat(paths).cpu().numpy()
         Un = torch.cat(U_net)
@@ -330,6 +333,7 @@ def foldin_report(torch, prob, gpu_csr, head_als, M, stream, dev, args, tol=1e-3
                     "speedup_vs_exact_only": t_exact / t_net,
                     "residual_quantiles": {q: float(np.quantile(fin, q)) for q in (0.1, 0.5, 0.9)},
                     "acceptance_if_tol": {str(t): float(np.mean(rho <= t)) for t in (1e-2, 3e-2, 1e-1, 3e-1)},
+                    "speedup_vs_exact_only_if_tol": {str(t): t_exact / tl for t, tl in t_loose.items()},
                     "kept_answer_rel_diff_to_exact_max": float(diff[torch.from_numpy(kept).to(dev)].max().item())
                     if kept.any() else None,
                     # the check kernels solve without the Woodbury form of the smallest
