@@ -475,7 +475,15 @@ __device__ __forceinline__ int pivot_key(const float (&A)[NF], int lane, int my_
 // pk: with PIVOT, the wave's maximum pivot key of column J, computed by the
 // previous step as soon as column J was final (lookahead: the reduction runs
 // beside the rest of that step's update); on return, the key of column J + 1.
-template <bool PIVOT, int NR, int J, bool KEEP>
+// Bounds under which an elimination without row exchanges is kept: entries of
+// the eliminated matrix within UNPIV_GROWTH max|A|, multipliers within
+// UNPIV_MULT in magnitude.
+constexpr float UNPIV_GROWTH = 4.f;
+constexpr float UNPIV_MULT = 4.f;
+
+// MCHK (without pivoting only): a multiplier above UNPIV_MULT in magnitude
+// clears the lane's ok, which is then no longer uniform over the wave.
+template <bool PIVOT, int NR, int J, bool KEEP, bool MCHK = false>
 __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], int lane, int nf, float tol,
                                             int &my_step, bool &ok, int &pk) {
     int p;
@@ -489,6 +497,7 @@ __device__ __forceinline__ void elim_step_u(float (&A)[NF], float (&rhs)[NR], in
     }
     const float piv = readlane_f(A[J], p);
     ok = ok && (J >= nf || fabsf(piv) > tol);
+    if constexpr (MCHK) ok = ok && !(lane > J && fabsf(A[J]) > UNPIV_MULT * fabsf(piv));
     const bool elim = active && lane != p;
     // multipliers by the hardware reciprocal (1 ulp) instead of an IEEE
     // division sequence: one uniform reciprocal per step
@@ -623,11 +632,11 @@ __device__ __forceinline__ void back_step_u(const float (&A)[NF], float (&rhs)[N
     }
 }
 
-template <bool PIVOT, int NR, bool KEEP, int... J>
+template <bool PIVOT, int NR, bool KEEP, bool MCHK = false, int... J>
 __device__ __forceinline__ void elim_all_u(std::integer_sequence<int, J...>, float (&A)[NF], float (&rhs)[NR],
                                            int lane, int nf, float tol, int &my_step, bool &ok) {
     int pk = PIVOT ? pivot_key<0>(A, lane, my_step) : 0;
-    (elim_step_u<PIVOT, NR, J, KEEP>(A, rhs, lane, nf, tol, my_step, ok, pk), ...);
+    (elim_step_u<PIVOT, NR, J, KEEP, MCHK>(A, rhs, lane, nf, tol, my_step, ok, pk), ...);
 }
 
 // Forward elimination of a new right-hand side with kept factors: at step J
@@ -703,8 +712,6 @@ __device__ __forceinline__ bool solve(float (&A)[NF], float rhs, int lane, int n
 // factors have the backward error bound of the pivoted LU up to those
 // factors.  Returns false otherwise; A is then spent and the caller builds
 // the system again for the pivoted LU.
-constexpr float UNPIV_GROWTH = 4.f;
-constexpr float UNPIV_MULT = 4.f;
 // BLOCKED: panels as in solve_n (the heavy-row solve).
 template <class LDS, bool BLOCKED = false>
 __device__ __forceinline__ bool solve_unpivoted(float (&A)[NF], float rhs, int lane, int nf, float tol, float &u,
@@ -719,25 +726,28 @@ __device__ __forceinline__ bool solve_unpivoted(float (&A)[NF], float rhs, int l
     if constexpr (BLOCKED)
         blk_all<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok, L.pbuf);
     else
-        elim_all_u<false, 1, false>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok);
+        elim_all_u<false, 1, false, true>(std::make_integer_sequence<int, NF>{}, A, r, lane, nf, tol, my_step, ok);
     float g = 0.f;
 #pragma unroll
     for (int b = 0; b < NF; ++b) g = fmaxf(g, fabsf(A[b]));
     g = __int_as_float(wave_max_key(__float_as_int(g)));
-    if (!ok || !(g <= UNPIV_GROWTH * amax)) return false;
-    // the multipliers, from what the elimination left: column J of a row
-    // below J still holds that row's entry when it was eliminated, l u_JJ,
-    // and row J holds u_JJ
-    uint64_t big = 0;
+    if (__ballot(!ok) != 0 || !(g <= UNPIV_GROWTH * amax)) return false;
+    if constexpr (BLOCKED) {
+        // the multipliers, from what the elimination left: column J of a row
+        // below J still holds that row's entry when it was eliminated, l u_JJ,
+        // and row J holds u_JJ
+        uint64_t big = 0;
 #pragma unroll
-    for (int j0 = 0; j0 < NF; j0 += 8) {
-        float ud[8];
+        for (int j0 = 0; j0 < NF; j0 += 8) {
+            float ud[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) ud[t] = readlane_f(A[j0 + t], j0 + t);
+            for (int t = 0; t < 8; ++t) ud[t] = readlane_f(A[j0 + t], j0 + t);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) big |= __ballot(lane > j0 + t && fabsf(A[j0 + t]) > UNPIV_MULT * fabsf(ud[t]));
+            for (int t = 0; t < 8; ++t)
+                big |= __ballot(lane > j0 + t && fabsf(A[j0 + t]) > UNPIV_MULT * fabsf(ud[t]));
+        }
+        if (big) return false;
     }
-    if (big) return false;
     my_step = lane;
     wave_sync();
     back_all_u<false, 1>(std::make_integer_sequence<int, NF>{}, A, r, lane, my_step, L.urhs);
