@@ -16,6 +16,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -462,6 +463,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="time only r = 1/10 (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
+    ap.add_argument("--tune-out", default=os.path.join(tempfile.gettempdir(), "coreals_tuning_gfx950.json"),
+                    help="where a schedule search writes its trials (the committed cache is not modified)")
     ap.add_argument("--no-foldin", action="store_true", help="skip the learned fold-in section")
     ap.add_argument("--no-section5", action="store_true", help="skip the simulation-study section")
     ap.add_argument("--foldin-epochs", type=int, default=5)
@@ -504,10 +507,10 @@ def main():
                    torch.from_numpy(prob.val).to(dev))
     stream.synchronize()
     # schedules, one per (budget, precision): the committed tuning cache when
-    # it knows this problem, else a coordinate search on the box (written to
-    # gpurun_out/ for review); the fast and implicit variants take the
+    # it knows this problem, else a coordinate search on this GPU (written to
+    # --tune-out for review); the fast and implicit variants take the
     # per-row method's schedule of their budget
-    tune_out = os.path.join(ROOT, "gpurun_out", "tuning_gfx950.json")
+    tune_out = args.tune_out
     schedules = {}
     sig = autotune.degree_signature(prob.row_ptr, prob.col_idx, prob.n_m)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
