@@ -129,3 +129,33 @@ def test_traffic_figure_only_for_the_sources_it_was_taken_on(tmp_path, monkeypat
     assert bench.measured_traffic("k_heavy_gram_x6") is None
     json.dump(dict(entry, source_sha256="0" * 64), open(path, "w"))
     assert bench.measured_traffic("k_heavy_select") is None  # taken on other sources
+
+
+def test_tuner_coordinate_search_and_cache(tmp_path, monkeypatch):
+    """The schedule search with a synthetic cost (no GPU): two rounds of
+    coordinate descent reach the cost's minimum, every trial is recorded, and
+    a second call returns the cached setting without timing anything."""
+    import types
+    p = synth.random_problem(4, 120, 90, 8, 0.1)
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        get_device_properties=lambda i: types.SimpleNamespace(gcnArchName="gfx950:sramecc+:xnack-"),
+        Stream=lambda: None))
+    want = {"heavy_min_degree": 384, "heavy_chunk": 2048, "light_blocks": 1024}
+    calls = []
+
+    def cost(torch, prob, gpu_csr, budget, precision, cfg, stream, sweeps=2):
+        calls.append(dict(cfg))
+        # separable except for a coupling that a single round would miss
+        c = sum(abs(autotune.SPACE[k].index(cfg[k]) - autotune.SPACE[k].index(want[k])) for k in want)
+        return 10.0 + c + (0.5 if cfg["light_blocks"] == 0 and cfg["heavy_min_degree"] != 1024 else 0.0)
+
+    monkeypatch.setattr(autotune, "time_config", cost)
+    path = str(tmp_path / "cache.json")
+    best = autotune.tune(fake_torch, p, None, (1, 10), 0, stream=object(), path=path)
+    assert best == want
+    entry = next(iter(autotune.load_cache(path).values()))
+    assert entry["config"] == want and entry["ms_per_sweep"] == 10.0
+    assert len(entry["trials"]) == len(calls)
+    n = len(calls)
+    assert autotune.tune(fake_torch, p, None, (1, 10), 0, stream=object(), path=path) == want
+    assert len(calls) == n  # cached: nothing timed
